@@ -1,0 +1,158 @@
+/*
+ * nr.h — C ABI of the MI355X (gfx950) library for the specular neutron
+ * reflectivity log-likelihood and its exact gradient (arXiv 2509.06924).
+ *
+ * The operation (paper Sec. 2.1 problem statement, Sec. 3 API, Sec. 4.1 chi^2):
+ * for every item b (one parameter draw of one slab stack, bound to one
+ * dataset), and every data point Q_i of that dataset,
+ *
+ *   kz0 = Q/2,  kz_j = sqrt(kz0^2 - 4 pi (rho_re,j - rho_re,0) - i 4 pi |rho_im,j|)
+ *                  (root with Re >= 0, Im <= 0; fronting rho_im ignored)
+ *   r_j  = (kz_j - kz_{j+1}) / (kz_j + kz_{j+1})     interface j = 0..L
+ *   r'_j = r_j exp(-2 kz_j kz_{j+1} sigma_{j+1}^2)    (Nevot-Croce roughness)
+ *   M = C_0 C_1 ... C_L,  C_j = [[E_j, r'_j E_j], [r'_j/E_j, 1/E_j]],
+ *   E_j = exp(i kz_j d_j), E_0 = 1,   R(q) = |M10 / M00|^2      (Abeles)
+ *   R_sm(Q) = sum_k w_k R(q_k)   (17-point Gauss-Legendre rule over +-3.5
+ *             sigma_Q, sigma_Q = (dQ/Q) Q / (2 sqrt(2 ln 2)), normalised
+ *             Gaussian weights; a single node when dQ/Q = 0)
+ *   R_hat = scale * R_sm + bkg
+ *   logL_b = sum_i [ -1/2 ((R_hat_i - R_obs,i)/e_i)^2 - ln e_i - 1/2 ln 2 pi ]
+ *
+ * and the gradient of logL_b with respect to every entry of the item's rows
+ * and to its scale and background.
+ *
+ * Layouts (all arrays are caller-owned; "device" means HIP device memory):
+ *   Dataset s: points q_off[s] .. q_off[s+1]-1 of the packed arrays q,
+ *     r_obs, r_err (Angstrom^-1, absolute reflectivity, its standard error),
+ *     resolution dq_over_q[s] (FWHM fraction; 0 = no smearing).
+ *   Item b: rows row_off[b] .. row_off[b+1]-1 of `layers` (row-major, 4
+ *     doubles per row: [thickness d (A), SLD rho_re (A^-2, absolute), imaginary
+ *     SLD rho_im (A^-2), roughness sigma (A) of the interface above the row]);
+ *     row 0 = fronting (only rho_re is read), the last row = backing (d is not
+ *     read); L = rows - 2 finite layers, 0 <= L <= NR_MAX_LAYERS.  The item
+ *     reads dataset dataset_of_item[b], scale[b], bkg[b].
+ *   Gradient rows are packed exactly like `layers`; entries the model does not
+ *     read are written as 0.  Per item g_inst[2b] = d/dscale, g_inst[2b+1] =
+ *     d/dbkg.  d/d rho_im uses the one-sided derivative +1 of |x| at 0.
+ *
+ * Ownership and synchronisation: the library never allocates or frees inside
+ * the evaluation calls and never synchronises the stream; every call only
+ * enqueues work on `stream` and returns.  Pointers must stay valid until the
+ * enqueued work has finished.  A plan holds device copies of the batch
+ * structure (offsets, dataset map, work list) and may be used by one stream
+ * at a time.
+ *
+ * Errors: every call returns an nr_status.  Argument errors are detected on
+ * the host before anything is enqueued.  Data-dependent faults (non-finite
+ * values, Q or a node <= 0, e_i <= 0) cannot be seen without a sync: they set
+ * bits in the optional per-item status array and make that item's logL NaN.
+ */
+#ifndef NR_H_
+#define NR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NR_VERSION 1
+/* Largest number of finite layers one item may have. */
+#define NR_MAX_LAYERS 40
+/* Number of quadrature nodes per data point when dq_over_q > 0. */
+#define NR_SMEAR_NODES 17
+
+typedef int32_t nr_status;
+#define NR_OK 0
+#define NR_EINVAL 1     /* null pointer, bad count, bad offsets, bad option */
+#define NR_EWORKSPACE 2 /* workspace missing or smaller than required */
+#define NR_EHIP 3       /* a HIP runtime call or kernel launch failed */
+#define NR_ENOMEM 4     /* plan creation could not allocate device memory */
+
+/* Arithmetic precision of the bulk layer product.  The wavevector root,
+ * quadrature, smearing sums, chi^2 and gradient accumulation stay FP64. */
+#define NR_F64 0
+#define NR_F32 1
+
+/* Bits of the optional per-item status array (device int32[n_items]). */
+#define NR_ITEM_NONFINITE 1u /* a non-finite R, logL or gradient value */
+#define NR_ITEM_BAD_Q 2u     /* a data point or a quadrature node q <= 0 */
+#define NR_ITEM_BAD_ERR 4u   /* an error bar e_i <= 0 or non-finite */
+
+typedef struct nr_plan nr_plan;
+
+/* Batch structure, given as HOST arrays; copied into the plan. */
+typedef struct nr_batch_desc {
+  int32_t n_datasets;
+  const int64_t* q_off;           /* host [n_datasets + 1], q_off[0] = 0, non-decreasing */
+  const double* dq_over_q;        /* host [n_datasets], >= 0 and finite */
+  int32_t n_items;
+  const int32_t* dataset_of_item; /* host [n_items], each in [0, n_datasets) */
+  const int64_t* row_off;         /* host [n_items + 1], row_off[0] = 0, 2 <= rows <= NR_MAX_LAYERS + 2 */
+  int32_t precision;              /* NR_F64 or NR_F32 */
+} nr_batch_desc;
+
+/* Values of one evaluation, given as DEVICE pointers. */
+typedef struct nr_values {
+  const double* q;      /* [q_off[n_datasets]] */
+  const double* r_obs;  /* [q_off[n_datasets]] (unused by nr_reflectivity) */
+  const double* r_err;  /* [q_off[n_datasets]] (unused by nr_reflectivity) */
+  const double* layers; /* [row_off[n_items] * 4] */
+  const double* scale;  /* [n_items] */
+  const double* bkg;    /* [n_items] */
+  int32_t* item_status; /* optional [n_items]; NULL to skip; bits are OR-ed in */
+} nr_values;
+
+/* Operation selector for nr_workspace_size. */
+#define NR_OP_REFLECTIVITY 0
+#define NR_OP_LOGLIK 1
+#define NR_OP_LOGLIK_GRAD 2
+
+/* Library version (NR_VERSION). */
+int32_t nr_version(void);
+
+/* Human-readable text for a status code, or for NR_EHIP the last HIP error
+ * recorded on the calling thread.  Never returns NULL. */
+const char* nr_status_string(nr_status status);
+
+/* Builds a plan from the host batch description: validates it, builds the
+ * work list (one unit = one item x up to 64 consecutive points, ordered by
+ * decreasing cost) and uploads it to the current device.  Allocates device
+ * memory (owned by the plan; released by nr_plan_destroy).  Synchronous. */
+nr_status nr_plan_create(const nr_batch_desc* desc, nr_plan** plan_out);
+
+/* Releases a plan and its device memory.  NULL is accepted. */
+nr_status nr_plan_destroy(nr_plan* plan);
+
+/* Bytes of caller-provided device workspace that `op` needs for this plan
+ * (0 is possible).  Returns NR_EINVAL for an unknown op or a NULL plan. */
+nr_status nr_workspace_size(const nr_plan* plan, int32_t op, size_t* bytes);
+
+/* Packed output offsets: R_hat of item b starts at element out_off[b] of the
+ * nr_reflectivity output.  Fills host out_off[n_items + 1]. */
+nr_status nr_output_offsets(const nr_plan* plan, int64_t* out_off);
+
+/* Model curve (Abeles + smearing + instrument, Sec. 2.1 / Sec. 3): writes
+ * R_hat for every point of every item into device r_hat[out_off[n_items]],
+ * item-major, in the dataset's point order.  Needs no workspace. */
+nr_status nr_reflectivity(const nr_plan* plan, const nr_values* v, double* r_hat,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
+/* Gaussian log-likelihood per item (Sec. 2.1, Sec. 4.1 chi^2): writes device
+ * logL[n_items]. */
+nr_status nr_loglik(const nr_plan* plan, const nr_values* v, double* logL,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
+/* logL and its exact gradient (Sec. 2.1 AD figure, Sec. 3 gradient listing),
+ * by a hand-written adjoint of the layer product: writes device logL[n_items],
+ * g_rows[row_off[n_items] * 4] and g_inst[2 * n_items]. */
+nr_status nr_loglik_grad(const nr_plan* plan, const nr_values* v, double* logL,
+                         double* g_rows, double* g_inst, void* workspace,
+                         size_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NR_H_ */
