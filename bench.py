@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Throughput of the FP64 log-likelihood + exact gradient on one MI355X.
+
+Workload (default): 4096 parameter draws of a 10-layer stack sharing one
+dataset of 400 log-spaced Q points in [0.005, 0.35] 1/A with 5 % dQ/Q
+resolution (17 quadrature nodes per point), seeded synthetic inputs.  One
+step = one nr_loglik_grad call: per-item constants, quadrature nodes,
+wavevectors, interface and phase factors, layer product, smearing,
+instrument, chi^2 log-likelihood, adjoint seeds, adjoint re-walk and the
+gradient reduction, for every draw.  Inputs are resident in HBM before the
+timed region.
+
+Metric unit: layer-steps/s = sum over items of nodes x (L + 1) per second.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("logL+∇ evals/s (sample×Q×layer), FP64 vs plain; % of FP64 VALU peak")
+UNIT = "layer-steps/s"
+FP64_VALU_PEAK = 78.6e12  # MI355X dense FP64 vector, FLOP/s
+
+# Algorithmic FP64 operations per layer-step of the forward + reverse sweep
+# (operation count of the method; special functions at fixed costs:
+#  sqrt 10, divide 10, exp 20, sin+cos 40).  Derivation in the design doc.
+FLOP_FWD_PER_LAYER_STEP = 257
+FLOP_ADJ_PER_LAYER_STEP = 175
+FLOP_PER_LAYER_STEP = FLOP_FWD_PER_LAYER_STEP + FLOP_ADJ_PER_LAYER_STEP
+
+
+class _Hip:
+    """hipEvent helpers through the HIP runtime's C API."""
+
+    def __init__(self):
+        self.L = ctypes.CDLL("libamdhip64.so")
+        self.L.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.L.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                               ctypes.c_void_p]
+        self.L.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def event(self):
+        e = ctypes.c_void_p()
+        rc = self.L.hipEventCreate(ctypes.byref(e))
+        if rc != 0:
+            raise RuntimeError(f"hipEventCreate failed: {rc}")
+        return e
+
+    def elapsed_ms(self, a, b):
+        ms = ctypes.c_float()
+        rc = self.L.hipEventElapsedTime(ctypes.byref(ms), a, b)
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed: {rc}")
+        return float(ms.value)
+
+    def destroy(self, e):
+        self.L.hipEventDestroy(e)
+
+
+def make_workload(name):
+    from paper_2509_06924_amd import inputs
+    if name == "c2":
+        b = inputs.c2_batched()
+        cfg = {"workload": "4096 draws x 10-layer stack, 400 log-Q in [0.005,0.35], "
+                           "5% dQ/Q with 17-node quadrature, logL + exact gradient",
+               "draws": 4096, "layers": 10, "q_points": 400, "quad_nodes": 17,
+               "dq_over_q": 0.05}
+    elif name == "c1":
+        b = inputs.c1_single_film()
+        cfg = {"workload": "1 draw x 1-layer film, 200 log-Q in [0.008,0.3], unsmeared",
+               "draws": 1, "layers": 1, "q_points": 200, "quad_nodes": 1}
+    elif name == "c3":
+        b = inputs.c3_cofit()
+        cfg = {"workload": "1024 draws x 3 contrasts x 12 layers, Q 250/300/350, 5% dQ/Q",
+               "draws": 1024, "contrasts": 3, "layers": 12}
+    elif name == "c4":
+        b = inputs.c4_ragged()
+        cfg = {"workload": "16384 ragged items, L 2..40, nQ 100..1000, dQ/Q 2-8%",
+               "items": 16384}
+    elif name == "c5":
+        b = inputs.c5_vi()
+        cfg = {"workload": "8192 VI samples x 20 layers x 1000 Q, 5% dQ/Q", "samples": 8192,
+               "layers": 20}
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return b, cfg
+
+
+def cpu_baseline(batch, target_s=15.0):
+    """The oracle (CPU, FP64, complex-step gradient) on a bounded sample of the
+    same workload, all host threads; returns layer-steps/s of logL + gradient."""
+    import numpy as np
+
+    import oracle
+    nthreads = max(1, min(oracle.max_threads(), os.cpu_count() or 1, 16))
+
+    def run(items):
+        sub = batch.subset(items)
+        t0 = time.perf_counter()
+        oracle.loglik_grad_batch(sub.q_off, sub.Q, sub.Robs, sub.Rerr, sub.dq_over_q,
+                                 sub.dataset_of_item, sub.row_off, sub.layers, sub.scale,
+                                 sub.bkg, want_grad=True, nthreads=nthreads)
+        return time.perf_counter() - t0, sub.layer_steps()
+
+    t1, _ = run(np.arange(min(nthreads, batch.n_items)))
+    per_round = max(t1, 1e-3)
+    rounds = max(1, int(target_s / per_round))
+    n = min(batch.n_items, rounds * nthreads)
+    t, ls = run(np.arange(n))
+    return {"value": ls / t, "unit": UNIT, "cores": nthreads, "kind": "oracle",
+            "sample": f"first {n} items of the workload ({ls:.3e} layer-steps, {t:.1f} s, "
+                      f"complex-step gradient, OpenMP over items)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(items shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2509_06924_amd as nr
+    from paper_2509_06924_amd import _native
+
+    if not torch.cuda.is_available():
+        print("no GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    batch, cfg = make_workload(args.workload)
+    prob = nr.Problem.from_batch(batch, device="cuda:0")
+    out = (torch.empty(batch.n_items, dtype=torch.float64, device="cuda:0"),
+           torch.empty_like(prob.layers),
+           torch.empty(batch.n_items, 2, dtype=torch.float64, device="cuda:0"))
+    layer_steps = batch.layer_steps()
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        prob.loglik_grad(out=out, stream=stream)
+    torch.cuda.synchronize()
+
+    hip = _Hip()
+    evs = [(hip.event(), hip.event()) for _ in range(args.steps)]
+    L = _native.lib()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        _native.check(L.nr_plan_set_timing_events(prob.plan.handle, evs[k][0], evs[k][1]))
+        prob.loglik_grad(out=out, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _native.check(L.nr_plan_set_timing_events(prob.plan.handle, None, None))
+    wall = t1 - t0
+    kern_ms = [hip.elapsed_ms(a, b) for a, b in evs]
+    for a, b in evs:
+        hip.destroy(a)
+        hip.destroy(b)
+    kern_s = sum(kern_ms) / len(kern_ms) / 1e3
+    ms_per_step = wall / args.steps * 1e3
+    value = layer_steps * args.steps / wall
+    ok = bool(torch.isfinite(out[0]).all().item() and torch.isfinite(out[1]).all().item())
+
+    flops = FLOP_PER_LAYER_STEP * layer_steps
+    achieved = flops / kern_s
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded stand-in; the paper's datasets are not available)",
+        "config": cfg,
+        "layer_steps_per_step": layer_steps,
+        "draw_q_per_s": batch.data_points() * args.steps / wall,
+        "finite": ok,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": FP64_VALU_PEAK / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_VALU_PEAK,
+            "traffic": None,
+            "kernel": "k_loglik_grad (layer product, smearing, logL and adjoint)",
+            "kernel_ms": kern_s * 1e3,
+            "flop_per_layer_step": FLOP_PER_LAYER_STEP,
+        },
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -151,6 +151,13 @@ nr_status nr_loglik_grad(const nr_plan* plan, const nr_values* v, double* logL,
                          double* g_rows, double* g_inst, void* workspace,
                          size_t workspace_bytes, void* stream);
 
+/* Optional timing hooks for profiling: while set, every evaluation call
+ * records `start` (a hipEvent_t owned by the caller) on its stream just
+ * before its first layer-product kernel and `stop` just after its last one,
+ * so that the events bracket the dominant kernels and exclude the per-item
+ * reduction.  Pass NULL for both to disable.  Never synchronises. */
+nr_status nr_plan_set_timing_events(nr_plan* plan, void* start, void* stop);
+
 #ifdef __cplusplus
 }
 #endif

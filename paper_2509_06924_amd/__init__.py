@@ -1,0 +1,253 @@
+"""MI355X-native reflectivity log-likelihood and exact gradient (arXiv 2509.06924).
+
+The Python layer only marshals arguments: device memory and streams come from
+PyTorch, every step of the computation runs in the HIP library libnr.so
+(C ABI in include/nr.h).  There is no CPU fallback: if the library is missing
+the calls raise.
+
+    prob = Problem.from_batch(batch, device="cuda")
+    logL, g_rows, g_inst = prob.loglik_grad()
+    logL = NRLogLik.apply(layers, scale, bkg, prob)   # autograd
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _native as _n
+from ._native import (NR_F32, NR_F64, NR_ITEM_BAD_ERR, NR_ITEM_BAD_Q,  # noqa: F401
+                      NR_ITEM_NONFINITE, NR_MAX_LAYERS, NR_OP_LOGLIK,
+                      NR_OP_LOGLIK_GRAD, NR_OP_REFLECTIVITY, NativeError)
+
+__all__ = ["Plan", "Problem", "NRLogLik", "nr_reflectivity", "nr_loglik", "nr_loglik_grad",
+           "pack_theta", "NativeError"]
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None and a.size else None
+
+
+class Plan:
+    """Owns an nr_plan built from host batch structure."""
+
+    def __init__(self, q_off, dq_over_q, dataset_of_item, row_off, precision=NR_F64):
+        self.q_off = np.ascontiguousarray(q_off, np.int64)
+        self.dq_over_q = np.ascontiguousarray(dq_over_q, np.float64)
+        self.dataset_of_item = np.ascontiguousarray(dataset_of_item, np.int32)
+        self.row_off = np.ascontiguousarray(row_off, np.int64)
+        d = _n.BatchDesc(self.dq_over_q.size, _ptr(self.q_off), _ptr(self.dq_over_q),
+                         self.dataset_of_item.size, _ptr(self.dataset_of_item),
+                         _ptr(self.row_off), precision)
+        # q_off / row_off are never empty (n+1 entries)
+        d.q_off = ctypes.c_void_p(self.q_off.ctypes.data)
+        d.row_off = ctypes.c_void_p(self.row_off.ctypes.data)
+        h = ctypes.c_void_p()
+        _n.check(_n.lib().nr_plan_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.n_items = int(self.dataset_of_item.size)
+        self.n_datasets = int(self.dq_over_q.size)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace_size(self, op):
+        n = ctypes.c_size_t()
+        _n.check(_n.lib().nr_workspace_size(self._h, op, ctypes.byref(n)))
+        return int(n.value)
+
+    def output_offsets(self):
+        out = np.zeros(self.n_items + 1, np.int64)
+        _n.check(_n.lib().nr_output_offsets(self._h, ctypes.c_void_p(out.ctypes.data)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _n.lib().nr_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dp(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _values(q, r_obs, r_err, layers, scale, bkg, item_status=None):
+    return _n.Values(_dp(q), _dp(r_obs), _dp(r_err), _dp(layers), _dp(scale), _dp(bkg),
+                     _dp(item_status))
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def nr_reflectivity(plan, values, r_hat, workspace=None, stream=None):
+    ws = _dp(workspace)
+    nb = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _n.check(_n.lib().nr_reflectivity(plan.handle, ctypes.byref(values), _dp(r_hat), ws, nb,
+                                      _stream(stream)))
+
+
+def nr_loglik(plan, values, logL, workspace, stream=None):
+    nb = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _n.check(_n.lib().nr_loglik(plan.handle, ctypes.byref(values), _dp(logL), _dp(workspace),
+                                nb, _stream(stream)))
+
+
+def nr_loglik_grad(plan, values, logL, g_rows, g_inst, workspace, stream=None):
+    nb = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _n.check(_n.lib().nr_loglik_grad(plan.handle, ctypes.byref(values), _dp(logL), _dp(g_rows),
+                                     _dp(g_inst), _dp(workspace), nb, _stream(stream)))
+
+
+class Problem:
+    """Datasets resident on the device plus a plan; parameters may be swapped
+    per call (same structure)."""
+
+    def __init__(self, plan, q, r_obs, r_err, layers, scale, bkg, device="cuda"):
+        import torch
+        self.plan = plan
+        self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        f = dict(dtype=torch.float64, device=self.device)
+        self.q = torch.as_tensor(q, **f).contiguous()
+        self.r_obs = torch.as_tensor(r_obs, **f).contiguous()
+        self.r_err = torch.as_tensor(r_err, **f).contiguous()
+        self.layers = torch.as_tensor(layers, **f).reshape(-1, 4).contiguous()
+        self.scale = torch.as_tensor(scale, **f).contiguous()
+        self.bkg = torch.as_tensor(bkg, **f).contiguous()
+        self.item_status = torch.zeros(plan.n_items, dtype=torch.int32, device=self.device)
+        self._ws = {}
+        self.out_off = plan.output_offsets()
+
+    @classmethod
+    def from_batch(cls, batch, device="cuda", precision=NR_F64):
+        plan = Plan(batch.q_off, batch.dq_over_q, batch.dataset_of_item, batch.row_off, precision)
+        return cls(plan, batch.Q, batch.Robs, batch.Rerr, batch.layers, batch.scale, batch.bkg,
+                   device)
+
+    def workspace(self, op):
+        import torch
+        if op not in self._ws:
+            n = self.plan.workspace_size(op)
+            self._ws[op] = torch.empty(max(1, (n + 7) // 8), dtype=torch.float64,
+                                       device=self.device)
+        return self._ws[op]
+
+    def values(self, layers=None, scale=None, bkg=None):
+        layers = self.layers if layers is None else layers
+        scale = self.scale if scale is None else scale
+        bkg = self.bkg if bkg is None else bkg
+        for t in (layers, scale, bkg):
+            if t.dtype != self.q.dtype or t.device != self.device or not t.is_contiguous():
+                raise ValueError("parameters must be contiguous float64 tensors on the device")
+        if layers.numel() != self.layers.numel() or scale.numel() != self.plan.n_items \
+                or bkg.numel() != self.plan.n_items:
+            raise ValueError("parameter sizes do not match the plan")
+        return _values(self.q, self.r_obs, self.r_err, layers, scale, bkg, self.item_status)
+
+    def reflectivity(self, layers=None, scale=None, bkg=None, stream=None):
+        import torch
+        out = torch.empty(int(self.out_off[-1]), dtype=torch.float64, device=self.device)
+        nr_reflectivity(self.plan, self.values(layers, scale, bkg), out, None, stream)
+        return out
+
+    def loglik(self, layers=None, scale=None, bkg=None, stream=None):
+        import torch
+        out = torch.empty(self.plan.n_items, dtype=torch.float64, device=self.device)
+        nr_loglik(self.plan, self.values(layers, scale, bkg), out,
+                  self.workspace(NR_OP_LOGLIK), stream)
+        return out
+
+    def loglik_grad(self, layers=None, scale=None, bkg=None, stream=None, out=None):
+        import torch
+        if out is None:
+            out = (torch.empty(self.plan.n_items, dtype=torch.float64, device=self.device),
+                   torch.empty_like(self.layers),
+                   torch.empty(self.plan.n_items, 2, dtype=torch.float64, device=self.device))
+        logL, g_rows, g_inst = out
+        nr_loglik_grad(self.plan, self.values(layers, scale, bkg), logL, g_rows, g_inst,
+                       self.workspace(NR_OP_LOGLIK_GRAD), stream)
+        return logL, g_rows, g_inst
+
+
+def _make_autograd():
+    import torch
+
+    class NRLogLik(torch.autograd.Function):
+        """logL per item as a differentiable function of (layers, scale, bkg).
+
+        Forward runs the fused value+gradient kernel when any input needs a
+        gradient and keeps the gradient; backward scales it by grad_output."""
+
+        @staticmethod
+        def forward(ctx, layers, scale, bkg, problem):
+            need = any(ctx.needs_input_grad[:3])
+            if need:
+                logL, g_rows, g_inst = problem.loglik_grad(layers.detach().contiguous(),
+                                                           scale.detach().contiguous(),
+                                                           bkg.detach().contiguous())
+                ctx.save_for_backward(g_rows, g_inst)
+                ctx.row_item = problem.row_item
+            else:
+                logL = problem.loglik(layers.detach().contiguous(), scale.detach().contiguous(),
+                                      bkg.detach().contiguous())
+            return logL
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            g_rows, g_inst = ctx.saved_tensors
+            go_rows = grad_out[ctx.row_item].unsqueeze(1)
+            return g_rows * go_rows, g_inst[:, 0] * grad_out, g_inst[:, 1] * grad_out, None
+
+    return NRLogLik
+
+
+class _LazyAutograd:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _LazyAutograd._cls is None:
+            _LazyAutograd._cls = _make_autograd()
+        return getattr(_LazyAutograd._cls, name)
+
+
+NRLogLik = _LazyAutograd()
+
+
+def _row_item(problem):
+    import torch
+    ro = problem.plan.row_off
+    idx = np.repeat(np.arange(problem.plan.n_items), np.diff(ro))
+    return torch.as_tensor(idx, dtype=torch.int64, device=problem.device)
+
+
+Problem.row_item = property(lambda self: self.__dict__.setdefault("_row_item", _row_item(self)))
+
+
+def pack_theta(theta, sld_unit=1.0):
+    """Rows [d, rho_re, rho_im, sigma] from the paper's parameter dict
+    (Sec. 3): thick (n,), SLD (n+2,), rough (n+1,), optional iSLD (n+2,).
+    sld_unit multiplies SLD values (1e-6 for values given in 1e-6 A^-2)."""
+    thick = np.atleast_1d(np.asarray(theta["thick"], np.float64))
+    sld = np.atleast_1d(np.asarray(theta["SLD"], np.float64)) * sld_unit
+    rough = np.atleast_1d(np.asarray(theta["rough"], np.float64))
+    n = thick.size
+    if sld.size != n + 2 or rough.size != n + 1:
+        raise ValueError("expected thick (n,), SLD (n+2,), rough (n+1,)")
+    rows = np.zeros((n + 2, 4))
+    rows[1:n + 1, 0] = thick
+    rows[:, 1] = sld
+    if "iSLD" in theta:
+        rows[:, 2] = np.asarray(theta["iSLD"], np.float64) * sld_unit
+    rows[1:, 3] = rough
+    return rows

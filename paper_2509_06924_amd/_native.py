@@ -1,0 +1,96 @@
+"""ctypes binding of the C ABI declared in include/nr.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libnr.so")
+
+NR_OK, NR_EINVAL, NR_EWORKSPACE, NR_EHIP, NR_ENOMEM = 0, 1, 2, 3, 4
+NR_F64, NR_F32 = 0, 1
+NR_OP_REFLECTIVITY, NR_OP_LOGLIK, NR_OP_LOGLIK_GRAD = 0, 1, 2
+NR_ITEM_NONFINITE, NR_ITEM_BAD_Q, NR_ITEM_BAD_ERR = 1, 2, 4
+NR_MAX_LAYERS = 40
+NR_SMEAR_NODES = 17
+
+# every symbol include/nr.h declares
+EXPORTS = ("nr_version", "nr_status_string", "nr_plan_create", "nr_plan_destroy",
+           "nr_workspace_size", "nr_output_offsets", "nr_reflectivity", "nr_loglik",
+           "nr_loglik_grad", "nr_plan_set_timing_events")
+
+
+class BatchDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_datasets", ctypes.c_int32),
+        ("q_off", ctypes.c_void_p),
+        ("dq_over_q", ctypes.c_void_p),
+        ("n_items", ctypes.c_int32),
+        ("dataset_of_item", ctypes.c_void_p),
+        ("row_off", ctypes.c_void_p),
+        ("precision", ctypes.c_int32),
+    ]
+
+
+class Values(ctypes.Structure):
+    _fields_ = [
+        ("q", ctypes.c_void_p),
+        ("r_obs", ctypes.c_void_p),
+        ("r_err", ctypes.c_void_p),
+        ("layers", ctypes.c_void_p),
+        ("scale", ctypes.c_void_p),
+        ("bkg", ctypes.c_void_p),
+        ("item_status", ctypes.c_void_p),
+    ]
+
+
+class NativeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"nr status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libnr.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with python -m paper_2509_06924_amd.build "
+                "(the HIP library is the only implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        L.nr_version.restype = ctypes.c_int32
+        L.nr_status_string.restype = ctypes.c_char_p
+        L.nr_status_string.argtypes = [ctypes.c_int32]
+        L.nr_plan_create.restype = ctypes.c_int32
+        L.nr_plan_create.argtypes = [ctypes.POINTER(BatchDesc), ctypes.POINTER(P)]
+        L.nr_plan_destroy.restype = ctypes.c_int32
+        L.nr_plan_destroy.argtypes = [P]
+        L.nr_workspace_size.restype = ctypes.c_int32
+        L.nr_workspace_size.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+        L.nr_output_offsets.restype = ctypes.c_int32
+        L.nr_output_offsets.argtypes = [P, P]
+        L.nr_reflectivity.restype = ctypes.c_int32
+        L.nr_reflectivity.argtypes = [P, ctypes.POINTER(Values), P, P, ctypes.c_size_t, P]
+        L.nr_loglik.restype = ctypes.c_int32
+        L.nr_loglik.argtypes = [P, ctypes.POINTER(Values), P, P, ctypes.c_size_t, P]
+        L.nr_loglik_grad.restype = ctypes.c_int32
+        L.nr_loglik_grad.argtypes = [P, ctypes.POINTER(Values), P, P, P, P, ctypes.c_size_t, P]
+        L.nr_plan_set_timing_events.restype = ctypes.c_int32
+        L.nr_plan_set_timing_events.argtypes = [P, P, P]
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != NR_OK:
+        raise NativeError(status, lib().nr_status_string(status).decode())
+    return status
+
+
+def status_string(status):
+    return lib().nr_status_string(status).decode()

@@ -1,0 +1,81 @@
+// Internal interface between the C ABI (nr_api.hip) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "nr.h"
+
+namespace nr {
+
+constexpr int kSmearNodes = NR_SMEAR_NODES;
+constexpr int kMaxLayers = NR_MAX_LAYERS;
+constexpr int kWuPoints = 64;  // data points per work unit (one per lane)
+
+constexpr uint32_t kItemNonfinite = NR_ITEM_NONFINITE;
+constexpr uint32_t kItemBadQ = NR_ITEM_BAD_Q;
+constexpr uint32_t kItemBadErr = NR_ITEM_BAD_ERR;
+
+constexpr int kOpReflectivity = NR_OP_REFLECTIVITY;
+constexpr int kOpLoglik = NR_OP_LOGLIK;
+constexpr int kOpLoglikGrad = NR_OP_LOGLIK_GRAD;
+
+// Layer-count buckets: a kernel instantiated for LMAX serves items with
+// N <= LMAX finite layers (its layer loops are unrolled to LMAX and skip the
+// levels beyond N).
+#define NR_BUCKETS(X) X(1) X(2) X(4) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40)
+constexpr int kBucketLmax[] = {1, 2, 4, 6, 8, 10, 12, 16, 20, 24, 32, 40};
+constexpr int kNumBuckets = sizeof(kBucketLmax) / sizeof(int);
+
+inline int bucket_of(int N) {
+  for (int b = 0; b < kNumBuckets; ++b)
+    if (N <= kBucketLmax[b]) return b;
+  return -1;
+}
+
+struct KernelArgs {
+  // work list of one launch (launch order)
+  const int32_t* wu_item;
+  const int32_t* wu_p0;
+  const int64_t* wu_rec;
+  // batch structure (plan-owned device copies)
+  const int32_t* dataset_of_item;
+  const int64_t* q_off;
+  const int64_t* row_off;
+  const double* dq_over_q;
+  const int64_t* out_off;
+  // values (caller-owned)
+  const double* q;
+  const double* r_obs;
+  const double* r_err;
+  const double* layers;
+  const double* scale;
+  const double* bkg;
+  int32_t* item_status;
+  // outputs
+  double* out;  // nr_reflectivity
+  double* rec;  // workspace records
+  // quadrature rule (device, plan-owned): node offsets in units of sigma_Q,
+  // then normalised weights, kSmearNodes each
+  const double* rule;
+};
+
+struct ReduceArgs {
+  int32_t n_items;
+  const int64_t* item_wu_first;
+  const int32_t* item_wu_count;
+  const int64_t* rec_of_wu;
+  const double* rec;
+  const int64_t* row_off;
+  const double* layers;
+  double* logL;
+  double* g_rows;
+  double* g_inst;
+};
+
+hipError_t launch_forward(int op, const KernelArgs& a, int n_wu, hipStream_t st);
+hipError_t launch_grad(int bucket, const KernelArgs& a, int n_wu, hipStream_t st);
+hipError_t launch_reduce(int op, const ReduceArgs& a, hipStream_t st);
+
+}  // namespace nr

@@ -1,0 +1,488 @@
+// HIP kernels for gfx950: Abeles reflectivity with Nevot-Croce roughness,
+// Gaussian resolution smearing, instrument scale/background, Gaussian
+// log-likelihood, and the hand-written adjoint of the whole chain.
+//
+// Work decomposition: one work unit (WU) = one item x up to 64 consecutive data
+// points of its dataset, one wave (64 lanes) per WU, lane = data point.  The
+// item is wave-uniform, so its layer constants are staged once per wave in LDS
+// and read as broadcasts.  A lane walks all quadrature nodes of its point; for
+// each node it runs the layer product bottom-up (substrate -> surface) keeping
+// the two-component state of every level in registers, then the adjoint top
+// down, recomputing each layer's wavevector, interface coefficient and phase
+// instead of storing them.
+//
+// The layer product is written in a scaled form: the Abeles column
+// v_j = C_j v_{j+1} is divided by E_j at every layer, which leaves r = v1/v0
+// unchanged and turns the phase factor into e_j = E_j^-2 = exp(-2 i kz_j d_j),
+// whose modulus is <= 1 on the chosen branch (Im kz <= 0):
+//   P <- P + r'_j Qv,   Qv <- e_j (r'_j P + Qv),   starting from (1, 0).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "nr_device.hpp"
+#include "nr_internal.hpp"
+
+namespace nr {
+
+// ---------------------------------------------------------------------------
+// Per-item constants in LDS, indexed by medium m = 0..N+1 / interface j = 0..N
+//   A[m]  = 4 pi (rho_re,m - rho_re,0)        (A[0] = 0)
+//   B[m]  = 4 pi |rho_im,m|                   (B[0] = 0: fronting is lossless)
+//   D[m]  = 2 d_m                             (layers 1..N)
+//   C[j]  = -2 sigma_{j+1}^2                  (Nevot-Croce exponent factor)
+//   Nr/Ni[j] = w_j - w_{j+1} = (A[j+1]-A[j]) + i (B[j+1]-B[j]),
+//           the Q-independent numerator of r_j = (w_j - w_{j+1})/(kz_j + kz_{j+1})^2
+// ---------------------------------------------------------------------------
+struct ItemConsts {
+  double A[kMaxLayers + 2], B[kMaxLayers + 2], D[kMaxLayers + 2], C[kMaxLayers + 2],
+      Nr[kMaxLayers + 2], Ni[kMaxLayers + 2];
+  // smearing rule: node offsets (units of sigma_Q) and weights
+  double t[kSmearNodes], w[kSmearNodes];
+};
+
+// Reads of the staged constants are volatile so that the compiler re-reads
+// them from LDS at every use instead of keeping every layer's constants in
+// registers across the node loop.
+typedef __attribute__((address_space(3))) const volatile double lds_cv_double;
+__device__ __forceinline__ double ld(const double& x) {
+  return *(lds_cv_double*)(&x);
+}
+
+__device__ __forceinline__ void stage_item(ItemConsts& s, const double* rows, int N, int lane,
+                                           const double* rule) {
+  // rows: (N+2) x 4, [d, rho_re, rho_im, sigma]
+  if (lane <= N + 1) {
+    const double rho0 = rows[1];
+    const double* r = rows + 4 * lane;
+    s.A[lane] = (lane == 0) ? 0.0 : kFourPi * (r[1] - rho0);
+    s.B[lane] = (lane == 0) ? 0.0 : kFourPi * fabs(r[2]);
+    s.D[lane] = 2.0 * r[0];
+    if (lane <= N) {
+      const double sg = rows[4 * (lane + 1) + 3];
+      s.C[lane] = -2.0 * (sg * sg);
+    }
+  }
+  if (lane < kSmearNodes) {
+    s.t[lane] = rule[lane];
+    s.w[lane] = rule[kSmearNodes + lane];
+  }
+  __syncthreads();
+  if (lane <= N) {
+    s.Nr[lane] = s.A[lane + 1] - s.A[lane];
+    s.Ni[lane] = s.B[lane + 1] - s.B[lane];
+  }
+  __syncthreads();
+}
+
+// Interface quantities shared by the forward and adjoint sweeps.
+struct Iface {
+  cd s;   // 1/(kz_j + kz_{j+1})
+  cd r;   // Fresnel coefficient
+  cd f;   // Nevot-Croce factor
+  cd rp;  // r f
+  cd kk;  // kz_j kz_{j+1}
+};
+
+__device__ __forceinline__ Iface interface_coeffs(cd kzc, cd kzn, double Nr, double Ni, double C) {
+  Iface o;
+  o.s = crecip(kzc + kzn);
+  cd s2 = o.s * o.s;
+  // identical media: r = 0 exactly (also avoids 0 * inf when both kz vanish)
+  o.r = (Nr == 0.0 && Ni == 0.0) ? mk(0.0, 0.0) : mk(Nr, Ni) * s2;
+  o.kk = kzc * kzn;
+  o.f = cexp(C * o.kk);
+  o.rp = o.r * o.f;
+  return o;
+}
+
+// e_j = exp(-2 i kz_j d_j) = exp(D Im kz) cis(-D Re kz), D = 2 d_j.
+__device__ __forceinline__ cd layer_phase(cd kz, double D) {
+  return cexp(mk(D * kz.im, -D * kz.re));
+}
+
+// ---------------------------------------------------------------------------
+// Forward-only reflectivity of one node (no state kept; runtime layer loop).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double node_reflectivity(const ItemConsts& s, int N, double q) {
+  const double kz0sq = kz0_squared(q);
+  cd kzn = kz_root(kz_real_part(kz0sq, ld(s.A[N + 1])), -ld(s.B[N + 1]));
+  cd P = mk(1.0, 0.0), Qv = mk(0.0, 0.0);
+  for (int jj = N; jj >= 1; --jj) {
+    cd kzc = kz_root(kz_real_part(kz0sq, ld(s.A[jj])), -ld(s.B[jj]));
+    Iface it = interface_coeffs(kzc, kzn, ld(s.Nr[jj]), ld(s.Ni[jj]), ld(s.C[jj]));
+    cd Pn = P + it.rp * Qv;
+    cd t = it.rp * P + Qv;
+    Qv = layer_phase(kzc, ld(s.D[jj])) * t;
+    P = Pn;
+    kzn = kzc;
+  }
+  {
+    Iface it = interface_coeffs(mk(0.5 * q, 0.0), kzn, ld(s.Nr[0]), ld(s.Ni[0]), ld(s.C[0]));
+    cd Pn = P + it.rp * Qv;
+    Qv = it.rp * P + Qv;
+    P = Pn;
+  }
+  cd r = Qv * crecip(P);
+  return cabs2(r);
+}
+
+// Shared WU prologue.
+struct WuInfo {
+  int item, ds, N, nq, i;
+  int64_t qoff, roff;
+  bool active;
+  double Q, dqq;
+};
+
+__device__ __forceinline__ WuInfo wu_setup(const KernelArgs& a, int w, int lane) {
+  WuInfo u;
+  u.item = a.wu_item[w];
+  const int p0 = a.wu_p0[w];
+  u.ds = a.dataset_of_item[u.item];
+  u.qoff = a.q_off[u.ds];
+  u.nq = (int)(a.q_off[u.ds + 1] - u.qoff);
+  u.roff = a.row_off[u.item];
+  u.N = (int)(a.row_off[u.item + 1] - u.roff) - 2;
+  u.i = p0 + lane;
+  u.active = u.i < u.nq;
+  // idle lanes evaluate the WU's first point and discard the result
+  u.Q = a.q[u.qoff + (u.active ? u.i : p0)];
+  u.dqq = a.dq_over_q[u.ds];
+  return u;
+}
+
+__device__ __forceinline__ void flag(int32_t* status, int item, uint32_t bits) {
+  if (status != nullptr && bits != 0u) atomicOr(reinterpret_cast<unsigned int*>(status + item), bits);
+}
+
+// ---------------------------------------------------------------------------
+// R_hat per point (nr_reflectivity).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_reflectivity(KernelArgs a) {
+  __shared__ ItemConsts s;
+  const int lane = threadIdx.x;
+  const int w = blockIdx.x;
+  WuInfo u = wu_setup(a, w, lane);
+  stage_item(s, a.layers + 4 * u.roff, u.N, lane, a.rule);
+  const int K = (u.dqq > 0.0) ? kSmearNodes : 1;
+  double Rsm = 0.0;
+  bool badq = !(u.Q > 0.0);
+  for (int k = 0; k < K; ++k) {
+    const double q = (K == 1) ? u.Q : smear_node(u.Q, u.dqq, ld(s.t[k]));
+    badq |= !(q > 0.0);
+    const double wk = (K == 1) ? 1.0 : ld(s.w[k]);
+    Rsm += wk * node_reflectivity(s, u.N, q);
+  }
+  if (u.active) {
+    double Rhat = a.scale[u.item] * Rsm + a.bkg[u.item];
+    uint32_t bits = 0;
+    if (badq) {
+      Rhat = __builtin_nan("");
+      bits |= kItemBadQ;
+    }
+    if (!isfinite(Rhat)) bits |= kItemNonfinite;
+    flag(a.item_status, u.item, bits);
+    a.out[a.out_off[u.item] + u.i] = Rhat;
+  }
+}
+
+// Log-likelihood term of one point; sets status bits.
+__device__ __forceinline__ double point_loglik(double Rhat, double Robs, double e, bool badq,
+                                               uint32_t& bits) {
+  const double z = (Rhat - Robs) / e;
+  double ll = -0.5 * (z * z) - log(e) - kHalfLn2Pi;
+  if (!(e > 0.0) || !isfinite(e)) bits |= kItemBadErr;
+  if (badq) bits |= kItemBadQ;
+  if (bits) ll = __builtin_nan("");
+  if (!isfinite(ll)) bits |= kItemNonfinite;
+  return ll;
+}
+
+// ---------------------------------------------------------------------------
+// logL partial per WU (nr_loglik): record = 1 double.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_loglik(KernelArgs a) {
+  __shared__ ItemConsts s;
+  const int lane = threadIdx.x;
+  const int w = blockIdx.x;
+  WuInfo u = wu_setup(a, w, lane);
+  stage_item(s, a.layers + 4 * u.roff, u.N, lane, a.rule);
+  const int K = (u.dqq > 0.0) ? kSmearNodes : 1;
+  double Rsm = 0.0;
+  bool badq = !(u.Q > 0.0);
+  for (int k = 0; k < K; ++k) {
+    const double q = (K == 1) ? u.Q : smear_node(u.Q, u.dqq, ld(s.t[k]));
+    badq |= !(q > 0.0);
+    const double wk = (K == 1) ? 1.0 : ld(s.w[k]);
+    Rsm += wk * node_reflectivity(s, u.N, q);
+  }
+  double ll = 0.0;
+  uint32_t bits = 0;
+  if (u.active) {
+    const double Rhat = a.scale[u.item] * Rsm + a.bkg[u.item];
+    ll = point_loglik(Rhat, a.r_obs[u.qoff + u.i], a.r_err[u.qoff + u.i], badq, bits);
+  }
+  flag(a.item_status, u.item, bits);
+  ll = wave_sum(ll);
+  if (lane == 0) a.rec[a.wu_rec[w]] = ll;
+}
+
+// ---------------------------------------------------------------------------
+// logL + gradient partials per WU (nr_loglik_grad).
+// Record layout (NR = N + 2 media):
+//   [0] logL, [1] d/dscale, [2] d/dbkg,
+//   [3 + m]        sum Re wbar_m     (wbar_m = cotangent of w_m = kz_m^2)
+//   [3 + NR + m]   sum Im wbar_m
+//   [3 + 2NR + m]  sum dl/dd_m
+//   [3 + 3NR + m]  sum Re(conj(ubar) kz_{m-1} kz_m)   (sigma_m factor applied later)
+// ---------------------------------------------------------------------------
+template <int LMAX>
+__global__ __launch_bounds__(64) void k_loglik_grad(KernelArgs a) {
+  __shared__ ItemConsts s;
+  const int lane = threadIdx.x;
+  const int w = blockIdx.x;
+  WuInfo u = wu_setup(a, w, lane);
+  stage_item(s, a.layers + 4 * u.roff, u.N, lane, a.rule);
+  const int N = u.N;
+  const int K = (u.dqq > 0.0) ? kSmearNodes : 1;
+
+  // per-lane accumulators of sum_k w_k dR(q_k)/d(.)
+  cd Hw[LMAX + 2];
+  double Hd[LMAX + 2], Hs[LMAX + 2];
+#pragma unroll
+  for (int m = 0; m < LMAX + 2; ++m) {
+    Hw[m] = mk(0.0, 0.0);
+    Hd[m] = 0.0;
+    Hs[m] = 0.0;
+  }
+  cd tapeP[LMAX + 1], tapeQ[LMAX + 1];
+
+  double Rsm = 0.0;
+  bool badq = !(u.Q > 0.0);
+  for (int k = 0; k < K; ++k) {
+    const double q = (K == 1) ? u.Q : smear_node(u.Q, u.dqq, ld(s.t[k]));
+    badq |= !(q > 0.0);
+    const double wk = (K == 1) ? 1.0 : ld(s.w[k]);
+    const double kz0sq = kz0_squared(q);
+    const cd kz0 = mk(0.5 * q, 0.0);
+
+    // ---- forward, bottom-up, recording the state entering each level ----
+    cd kzn = kz_root(kz_real_part(kz0sq, ld(s.A[N + 1])), -ld(s.B[N + 1]));
+    cd P = mk(1.0, 0.0), Qv = mk(0.0, 0.0);
+#pragma unroll
+    for (int jj = LMAX; jj >= 0; --jj) {
+      if (jj <= N) {
+        cd kzc = (jj == 0) ? kz0 : kz_root(kz_real_part(kz0sq, ld(s.A[jj])), -ld(s.B[jj]));
+        tapeP[jj] = P;
+        tapeQ[jj] = Qv;
+        Iface it = interface_coeffs(kzc, kzn, ld(s.Nr[jj]), ld(s.Ni[jj]), ld(s.C[jj]));
+        cd Pn = P + it.rp * Qv;
+        cd t = it.rp * P + Qv;
+        Qv = (jj >= 1) ? layer_phase(kzc, ld(s.D[jj])) * t : t;
+        P = Pn;
+        kzn = kzc;
+      }
+      // keep the scheduler from hoisting later layers' work (register pressure)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    const cd iP = crecip(P);
+    const cd r = Qv * iP;
+    Rsm += wk * cabs2(r);
+
+    // ---- adjoint, top-down: l = w_k |r|^2 ----
+    const cd rbar = (2.0 * wk) * r;
+    cd Pb = cmulc(-(r * iP), rbar);  // conj(dr/dP) rbar, dr/dP = -r/P
+    cd Qb = cmulc(iP, rbar);         // conj(dr/dQv) rbar, dr/dQv = 1/P
+    cd kzc = kz0;
+    cd kzbc = mk(0.0, 0.0);
+#pragma unroll
+    for (int jj = 0; jj <= LMAX; ++jj) {
+      if (jj <= N) {
+        cd kzn2 = kz_root(kz_real_part(kz0sq, ld(s.A[jj + 1])), -ld(s.B[jj + 1]));
+        Iface it = interface_coeffs(kzc, kzn2, ld(s.Nr[jj]), ld(s.Ni[jj]), ld(s.C[jj]));
+        const cd Ps = tapeP[jj], Qs = tapeQ[jj];
+        const cd t = it.rp * Ps + Qs;
+        cd tb;
+        cd e = mk(1.0, 0.0), eb = mk(0.0, 0.0);
+        if (jj >= 1) {
+          e = layer_phase(kzc, ld(s.D[jj]));
+          eb = cmulc(t, Qb);
+          tb = cmulc(e, Qb);
+        } else {
+          tb = Qb;
+        }
+        // P_new = P + r' Qv ; t = r' P + Qv
+        const cd rpb = cmulc(Qs, Pb) + cmulc(Ps, tb);
+        const cd Pb_new = Pb + cmulc(it.rp, tb);
+        const cd Qb_new = cmulc(it.rp, Pb) + tb;
+        // r' = r f, f = exp(C kz_j kz_{j+1})
+        const cd rb = cmulc(it.f, rpb);
+        const cd ub = cmulc(it.rp, rpb);
+        kzbc += cmulc(ld(s.C[jj]) * kzn2, ub);
+        cd kzbn = cmulc(ld(s.C[jj]) * kzc, ub);
+        Hs[jj + 1] += ub.re * it.kk.re + ub.im * it.kk.im;
+        // r = (kz_j - kz_{j+1}) s: dr/dkz_j = 2 kz_{j+1} s^2, dr/dkz_{j+1} = -2 kz_j s^2
+        const cd s2 = it.s * it.s;
+        kzbc += cmulc(2.0 * (kzn2 * s2), rb);
+        kzbn += cmulc(-2.0 * (kzc * s2), rb);
+        if (jj >= 1) {
+          // e = exp(-2 i kz d): de/dkz = -i D e, de/dd = -2 i kz e
+          const double D = ld(s.D[jj]);
+          kzbc += cmulc(mk(D * e.im, -D * e.re), eb);
+          const cd ze = kzc * e;
+          Hd[jj] += eb.re * (2.0 * ze.im) + eb.im * (-2.0 * ze.re);
+          // w_j = kz_j^2: wbar = conj(1/(2 kz_j)) kzbar
+          Hw[jj] += cmulc(crecip(2.0 * kzc), kzbc);
+        }
+        if (jj == N) Hw[jj + 1] += cmulc(crecip(2.0 * kzn2), kzbn);
+        Pb = Pb_new;
+        Qb = Qb_new;
+        kzc = kzn2;
+        kzbc = kzbn;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+
+  // ---- instrument, likelihood, seeds ----
+  double ll = 0.0, gsc = 0.0, gbk = 0.0, fac = 0.0;
+  uint32_t bits = 0;
+  if (u.active) {
+    const double sc = a.scale[u.item];
+    const double Rhat = sc * Rsm + a.bkg[u.item];
+    const double e = a.r_err[u.qoff + u.i];
+    ll = point_loglik(Rhat, a.r_obs[u.qoff + u.i], e, badq, bits);
+    const double ghat = -(Rhat - a.r_obs[u.qoff + u.i]) / (e * e);
+    gsc = ghat * Rsm;
+    gbk = ghat;
+    fac = ghat * sc;
+  }
+  flag(a.item_status, u.item, bits);
+
+  // ---- wave reduction and record ----
+  double* rec = a.rec + a.wu_rec[w];
+  const int NR = N + 2;
+  ll = wave_sum(ll);
+  gsc = wave_sum(gsc);
+  gbk = wave_sum(gbk);
+  if (lane == 0) {
+    rec[0] = ll;
+    rec[1] = gsc;
+    rec[2] = gbk;
+  }
+#pragma unroll
+  for (int m = 0; m < LMAX + 2; ++m) {
+    if (m < NR) {
+      const double wr = wave_sum(fac * Hw[m].re);
+      const double wi = wave_sum(fac * Hw[m].im);
+      const double dd = wave_sum(fac * Hd[m]);
+      const double ss = wave_sum(fac * Hs[m]);
+      if (lane == 0) {
+        rec[3 + m] = wr;
+        rec[3 + NR + m] = wi;
+        rec[3 + 2 * NR + m] = dd;
+        rec[3 + 3 * NR + m] = ss;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic per-item reductions of the WU records.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_reduce_loglik(ReduceArgs a) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.n_items) return;
+  const int64_t first = a.item_wu_first[b];
+  const int cnt = a.item_wu_count[b];
+  double s = 0.0;
+  for (int k = 0; k < cnt; ++k) s += a.rec[a.rec_of_wu[first + k]];
+  a.logL[b] = s;
+}
+
+// One wave per item: lanes sum record fields over the item's WUs, then turn
+// the sums into gradients of the row entries.
+__global__ __launch_bounds__(64) void k_reduce_grad(ReduceArgs a) {
+  extern __shared__ double fsum[];
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t first = a.item_wu_first[b];
+  const int cnt = a.item_wu_count[b];
+  const int64_t roff = a.row_off[b];
+  const int NR = (int)(a.row_off[b + 1] - roff);
+  const int nf = 3 + 4 * NR;
+  for (int f = lane; f < nf; f += 64) {
+    double v = 0.0;
+    for (int k = 0; k < cnt; ++k) v += a.rec[a.rec_of_wu[first + k] + f];
+    fsum[f] = v;
+  }
+  __syncthreads();
+  const double* rows = a.layers + 4 * roff;
+  double* g = a.g_rows + 4 * roff;
+  for (int m = lane; m < NR; m += 64) {
+    const double wr = fsum[3 + m], wi = fsum[3 + NR + m];
+    const double dd = fsum[3 + 2 * NR + m], ss = fsum[3 + 3 * NR + m];
+    double gd = 0.0, gre = 0.0, gim = 0.0, gsig = 0.0;
+    if (m >= 1) {
+      gre = -kFourPi * wr;
+      const double sgn = (rows[4 * m + 2] < 0.0) ? -1.0 : 1.0;
+      gim = -kFourPi * sgn * wi;
+      gsig = -4.0 * rows[4 * m + 3] * ss;
+      if (m <= NR - 2) gd = dd;
+    }
+    g[4 * m + 0] = gd;
+    g[4 * m + 1] = gre;
+    g[4 * m + 2] = gim;
+    g[4 * m + 3] = gsig;
+  }
+  // fronting rho_re: the model depends on rho_re,m - rho_re,0 only
+  double part = 0.0;
+  for (int m = 1 + lane; m < NR; m += 64) part += fsum[3 + m];
+  part = wave_sum(part);
+  if (lane == 0) {
+    g[1] = kFourPi * part;
+    a.logL[b] = fsum[0];
+    a.g_inst[2 * b + 0] = fsum[1];
+    a.g_inst[2 * b + 1] = fsum[2];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_forward(int op, const KernelArgs& a, int n_wu, hipStream_t st) {
+  if (n_wu <= 0) return hipSuccess;
+  if (op == kOpReflectivity)
+    hipLaunchKernelGGL(k_reflectivity, dim3(n_wu), dim3(64), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_loglik, dim3(n_wu), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad(int bucket, const KernelArgs& a, int n_wu, hipStream_t st) {
+  if (n_wu <= 0) return hipSuccess;
+  switch (kBucketLmax[bucket]) {
+#define NR_CASE(LM)                                                                   \
+  case LM:                                                                            \
+    hipLaunchKernelGGL(k_loglik_grad<LM>, dim3(n_wu), dim3(64), 0, st, a);            \
+    return hipGetLastError();
+    NR_BUCKETS(NR_CASE)
+#undef NR_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_reduce(int op, const ReduceArgs& a, hipStream_t st) {
+  if (a.n_items <= 0) return hipSuccess;
+  if (op == kOpLoglik) {
+    hipLaunchKernelGGL(k_reduce_loglik, dim3((a.n_items + 255) / 256), dim3(256), 0, st, a);
+  } else {
+    const size_t shmem = sizeof(double) * (3 + 4 * (kMaxLayers + 2));
+    hipLaunchKernelGGL(k_reduce_grad, dim3(a.n_items), dim3(64), shmem, st, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace nr

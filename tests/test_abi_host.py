@@ -1,0 +1,109 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol include/nr.h declares, and rejects invalid batch descriptions
+before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2509_06924_amd import _native
+    if not os.path.exists(_native.LIB_PATH):
+        pytest.skip("libnr.so not built")
+    return _native, _native.lib()
+
+
+def test_header_declares_exactly_the_exported_api():
+    from paper_2509_06924_amd import _native
+    text = open(os.path.join(ROOT, "include", "nr.h")).read()
+    declared = set(re.findall(r"^\s*(?:nr_status|int32_t|const char\*)\s+(nr_\w+)\s*\(", text, re.M))
+    assert declared == set(_native.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    n, L = _lib()
+    for name in n.EXPORTS:
+        assert hasattr(L, name), name
+    assert L.nr_version() == 1
+
+
+def test_status_strings():
+    n, L = _lib()
+    for s in range(0, 6):
+        assert isinstance(n.status_string(s), str) and n.status_string(s)
+
+
+def _desc(n, q_off, dqq, dsi, row_off, precision=0):
+    keep = [np.ascontiguousarray(q_off, np.int64), np.ascontiguousarray(dqq, np.float64),
+            np.ascontiguousarray(dsi, np.int32), np.ascontiguousarray(row_off, np.int64)]
+    d = n.BatchDesc(len(dqq), ctypes.c_void_p(keep[0].ctypes.data),
+                    ctypes.c_void_p(keep[1].ctypes.data) if len(dqq) else None, len(dsi),
+                    ctypes.c_void_p(keep[2].ctypes.data) if len(dsi) else None,
+                    ctypes.c_void_p(keep[3].ctypes.data), precision)
+    return d, keep
+
+
+@pytest.mark.parametrize("case", [
+    "null", "neg_items", "bad_precision", "q_off_start", "q_off_decreasing", "neg_dqq",
+    "nan_dqq", "too_few_rows", "too_many_layers", "bad_dataset"])
+def test_invalid_descriptions_rejected(case):
+    n, L = _lib()
+    q_off, dqq, dsi, row_off, prec = [0, 10, 20], [0.05, 0.0], [0, 1], [0, 4, 7], 0
+    if case == "null":
+        h = ctypes.c_void_p()
+        assert L.nr_plan_create(None, ctypes.byref(h)) == n.NR_EINVAL
+        return
+    if case == "neg_items":
+        d, keep = _desc(n, q_off, dqq, dsi, row_off)
+        d.n_items = -1
+    else:
+        if case == "bad_precision":
+            prec = 7
+        elif case == "q_off_start":
+            q_off = [1, 10, 20]
+        elif case == "q_off_decreasing":
+            q_off = [0, 10, 5]
+        elif case == "neg_dqq":
+            dqq = [-0.01, 0.0]
+        elif case == "nan_dqq":
+            dqq = [float("nan"), 0.0]
+        elif case == "too_few_rows":
+            row_off = [0, 1, 4]
+        elif case == "too_many_layers":
+            row_off = [0, 4, 4 + n.NR_MAX_LAYERS + 3]
+        elif case == "bad_dataset":
+            dsi = [0, 2]
+        d, keep = _desc(n, q_off, dqq, dsi, row_off, prec)
+    h = ctypes.c_void_p()
+    assert L.nr_plan_create(ctypes.byref(d), ctypes.byref(h)) == n.NR_EINVAL
+    assert not h.value
+
+
+def test_null_plan_calls_rejected():
+    n, L = _lib()
+    sz = ctypes.c_size_t()
+    assert L.nr_workspace_size(None, 0, ctypes.byref(sz)) == n.NR_EINVAL
+    v = n.Values()
+    assert L.nr_loglik(None, ctypes.byref(v), None, None, 0, None) == n.NR_EINVAL
+    assert L.nr_loglik_grad(None, ctypes.byref(v), None, None, None, None, 0, None) == n.NR_EINVAL
+    assert L.nr_reflectivity(None, ctypes.byref(v), None, None, 0, None) == n.NR_EINVAL
+    assert L.nr_plan_destroy(None) == n.NR_OK
+
+
+def test_paper_parameter_dict_packs_to_rows():
+    """The Sec. 3 parameter dict (shapes only: n = 2 layers) maps to rows."""
+    import json
+    from paper_2509_06924_amd import pack_theta
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_theta_example.json")))
+    rows = pack_theta(g["theta"], sld_unit=1e-6)
+    n = len(g["theta"]["thick"])
+    assert rows.shape == (n + 2, 4)
+    assert np.array_equal(rows[1:n + 1, 0], g["theta"]["thick"])
+    assert np.allclose(rows[:, 1], np.array(g["theta"]["SLD"]) * 1e-6)
+    assert np.array_equal(rows[1:, 3], g["theta"]["rough"])
+    assert rows[0, 0] == 0 and rows[-1, 0] == 0 and rows[0, 3] == 0
