@@ -74,6 +74,17 @@ void smearing_rule(double* t, double* w) {
   for (int k = 0; k < kSmearNodes; ++k) w[k] = (double)(g[k] / total);
 }
 
+// Tables for the device exp and sincos, correctly rounded from long double:
+// (sin, cos)(k pi/32) for k = 0..63, interleaved, then 2^(j/64) for j = 0..63.
+void append_math_tables(std::vector<double>& v) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int k = 0; k < 64; ++k) {
+    v.push_back((double)std::sin(pi * k / 32.0L));
+    v.push_back((double)std::cos(pi * k / 32.0L));
+  }
+  for (int j = 0; j < 64; ++j) v.push_back((double)std::exp2((long double)j / 64.0L));
+}
+
 struct Launch {
   int bucket = 0;
   int n_wu = 0;
@@ -293,6 +304,7 @@ nr_status nr_plan_create(const nr_batch_desc* d, nr_plan** out) {
   if (e == hipSuccess) {
     std::vector<double> rule(p->node_t, p->node_t + kSmearNodes);
     rule.insert(rule.end(), p->node_w, p->node_w + kSmearNodes);
+    append_math_tables(rule);
     e = upload(&p->d_rule, rule);
     keep(p->d_rule);
   }

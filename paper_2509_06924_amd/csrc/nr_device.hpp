@@ -54,81 +54,103 @@ __device__ __forceinline__ cd crecip(cd z) {
   return mk(z.re * inv, -z.im * inv);
 }
 
-// sin and cos of x: FMA-based Cody-Waite reduction r = x - n pi/2 with pi/2
-// split into three doubles (|r| <= pi/4, accurate to a few ulp for
-// |x| < 2^40), Taylor series of sin to r^17 and of cos to r^18 (truncation
-// below 1e-19 on |r| <= pi/4), then the quadrant n mod 4.
-__device__ __forceinline__ void sincos_cw(double x, double* sn, double* cs) {
-  constexpr double kTwoOverPi = 0.6366197723675814;
-  constexpr double kP1 = 1.5707963267948966;
-  constexpr double kP2 = 6.123233995736766e-17;
-  constexpr double kP3 = -1.4973849048591698e-33;
-  const double n = rint(x * kTwoOverPi);
-  double r = fma(-n, kP1, x);
-  r = fma(-n, kP2, r);
-  r = fma(-n, kP3, r);
-  const double r2 = r * r;
-  // sin r = r + r^3 ps,  ps = -1/3! + r^2/5! - ... + r^14/17!
-  double ps = 2.8114572543455206e-15;
-  ps = fma(ps, r2, -7.647163731819816e-13);
-  ps = fma(ps, r2, 1.6059043836821613e-10);
-  ps = fma(ps, r2, -2.505210838544172e-08);
-  ps = fma(ps, r2, 2.7557319223985893e-06);
-  ps = fma(ps, r2, -0.0001984126984126984);
-  ps = fma(ps, r2, 0.008333333333333333);
-  ps = fma(ps, r2, -0.16666666666666666);
-  const double s_r = fma(r * r2, ps, r);
-  // cos r = 1 - (r^2/2 - r^4 pc),  pc = 1/4! - r^2/6! + ... - r^14/18!
-  double pc = -1.5619206968586225e-16;
-  pc = fma(pc, r2, 4.779477332387385e-14);
-  pc = fma(pc, r2, -1.1470745597729725e-11);
-  pc = fma(pc, r2, 2.08767569878681e-09);
-  pc = fma(pc, r2, -2.755731922398589e-07);
-  pc = fma(pc, r2, 2.48015873015873e-05);
-  pc = fma(pc, r2, -0.001388888888888889);
-  pc = fma(pc, r2, 0.041666666666666664);
-  const double c_r = 1.0 - fma(-(r2 * r2), pc, 0.5 * r2);
-  // quadrant q = n mod 4 (exact for |n| < 2^53)
-  const int q = (int)(n - 4.0 * floor(0.25 * n));
-  const double s_sw = (q & 1) ? c_r : s_r;
-  const double c_sw = (q & 1) ? s_r : c_r;
-  *sn = (q & 2) ? -s_sw : s_sw;
-  *cs = ((q + 1) & 2) ? -c_sw : c_sw;
+// 1/sqrt(a) from the hardware estimate v_rsq_f64 (about 2^-24 relative)
+// refined by two Newton steps y <- y + y/2 (1 - a y^2).
+__device__ __forceinline__ double rsq(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  double e = fma(-(a * y), y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-(a * y), y, 1.0);
+  return fma(0.5 * y, e, y);
 }
 
-// e^x: reduction x = n ln2 + r, |r| <= ln2/2 (ln2 split into two doubles),
-// Taylor series of e^r to r^13 (truncation < 5e-18), scaling by 2^n.
-// Saturates to +inf above ~709.8 and to 0 below ~-745.
-__device__ __forceinline__ double exp_cw(double x) {
-  constexpr double kLog2e = 1.4426950408889634;
-  constexpr double kLn2Hi = 0.6931471805599453;
-  constexpr double kLn2Lo = 2.3190468138462996e-17;
-  double n = rint(x * kLog2e);
-  n = fmin(fmax(n, -1100.0), 1100.0);
-  double r = fma(-n, kLn2Hi, x);
-  r = fma(-n, kLn2Lo, r);
-  double p = 1.6059043836821613e-10;  // 1/13!
-  p = fma(p, r, 2.08767569878681e-09);
-  p = fma(p, r, 2.505210838544172e-08);
-  p = fma(p, r, 2.755731922398589e-07);
-  p = fma(p, r, 2.7557319223985893e-06);
-  p = fma(p, r, 2.48015873015873e-05);
-  p = fma(p, r, 0.0001984126984126984);
-  p = fma(p, r, 0.001388888888888889);
+// ---------------------------------------------------------------------------
+// Table-driven exp and sincos.  The tables live in LDS, filled per block from
+// plan-owned device memory computed on the host in long double:
+//   sc[k] = (sin(k pi/32), cos(k pi/32)), k = 0..63
+//   e2[j] = 2^(j/64),                       j = 0..63
+// ---------------------------------------------------------------------------
+struct MathTables {
+  double sc[64][2];
+  double e2[64];
+};
+constexpr int kTableDoubles = 64 * 2 + 64;
+
+typedef __attribute__((address_space(3))) const double lds_double;
+
+// Round-to-nearest integer of a double by the 1.5 * 2^52 shift: for
+// |v| < 2^51, t = v + kShift holds round(v) in its low mantissa bits, so
+// t - kShift is round(v) as a double and the low word of t is round(v)
+// modulo 2^32 (two's complement).
+constexpr double kShift = 6755399441055744.0;
+__device__ __forceinline__ int low_word(double t) {
+  return (int)(unsigned int)__double_as_longlong(t);
+}
+
+// sin and cos of x: x = k pi/32 + r with pi/32 split in three doubles (FMA
+// Cody-Waite, |r| <= pi/64, accurate for |x| < 2^40), Taylor polynomials of
+// sin r to r^9 and cos r to r^8 (truncation < 1e-19 on |r| <= pi/64), then
+// the angle-addition formulas with the tabulated sin/cos of (k mod 64) pi/32.
+__device__ __forceinline__ void sincos_tab(const MathTables& T, double x, double* sn,
+                                           double* cs) {
+  constexpr double k32OverPi = 10.185916357881302;
+  constexpr double kP1 = 0.09817477042468103;
+  constexpr double kP2 = 3.827021247335479e-18;
+  constexpr double kP3 = -9.358655655369811e-35;
+  const double t = fma(x, k32OverPi, kShift);
+  const double k = t - kShift;
+  double r = fma(-k, kP1, x);
+  r = fma(-k, kP2, r);
+  r = fma(-k, kP3, r);
+  const int idx = low_word(t) & 63;
+  const lds_double* row = (const lds_double*)(&T.sc[idx][0]);
+  const double sa = row[0], ca = row[1];
+  const double r2 = r * r;
+  double ps = 2.7557319223985893e-06;          //  1/9!
+  ps = fma(ps, r2, -0.0001984126984126984);    // -1/7!
+  ps = fma(ps, r2, 0.008333333333333333);      //  1/5!
+  ps = fma(ps, r2, -0.16666666666666666);      // -1/3!
+  const double sr = fma(r * r2, ps, r);
+  double pc = 2.48015873015873e-05;            //  1/8!
+  pc = fma(pc, r2, -0.001388888888888889);     // -1/6!
+  pc = fma(pc, r2, 0.041666666666666664);      //  1/4!
+  pc = fma(pc, r2, -0.5);                      // -1/2
+  const double cr = fma(r2, pc, 1.0);
+  *sn = fma(sa, cr, ca * sr);
+  *cs = fma(ca, cr, -(sa * sr));
+}
+
+// e^x: x = (64 m + j) ln2/64 + r with ln2/64 split in two doubles,
+// |r| <= ln2/128, Taylor polynomial of e^r to r^6 (truncation < 3e-20),
+// times the tabulated 2^(j/64), scaled by 2^m.  The argument is clamped to
+// [-746, 710] first: +inf above ~709.8, 0 below ~-745.
+__device__ __forceinline__ double exp_tab(const MathTables& T, double x) {
+  constexpr double k64OverLn2 = 92.33248261689366;
+  constexpr double kL1 = 0.010830424696249145;
+  constexpr double kL2 = 3.623510646634843e-19;
+  x = fmin(fmax(x, -746.0), 710.0);
+  const double t = fma(x, k64OverLn2, kShift);
+  const double n = t - kShift;
+  double r = fma(-n, kL1, x);
+  r = fma(-n, kL2, r);
+  const int ni = low_word(t);
+  const int j = ni & 63;
+  const int m = ni >> 6;  // floor(n / 64)
+  double p = 0.001388888888888889;   // 1/6!
   p = fma(p, r, 0.008333333333333333);
   p = fma(p, r, 0.041666666666666664);
   p = fma(p, r, 0.16666666666666666);
   p = fma(p, r, 0.5);
   p = fma(p, r, 1.0);
   p = fma(p, r, 1.0);
-  return ldexp(p, (int)n);
+  const double tj = ((const lds_double*)(&T.e2[0]))[j];
+  return ldexp(tj * p, m);
 }
 
-// exp(z) = e^{Re z} (cos Im z + i sin Im z)
-__device__ __forceinline__ cd cexp(cd z) {
+__device__ __forceinline__ cd cexp_tab(const MathTables& T, cd z) {
   double s, c;
-  sincos_cw(z.im, &s, &c);
-  const double e = exp_cw(z.re);
+  sincos_tab(T, z.im, &s, &c);
+  const double e = exp_tab(T, z.re);
   return mk(e * c, e * s);
 }
 
@@ -145,16 +167,28 @@ __device__ __forceinline__ double kz0_squared(double q) {
   return h * q;
 }
 
-// Root of w = x + i y (y <= 0) with Re >= 0, Im <= 0:
+// Root of w = x + i y (y <= 0) with Re >= 0, Im <= 0, and 1/|w| = 1/|kz|^2:
 //   t = sqrt((|w| + |x|)/2), o = y/(2t) (<= 0);  x >= 0 -> (t, o), x < 0 -> (-o, -t).
 // A zero y with x < 0 gives (0, -sqrt|x|) whatever the sign of that zero.
-__device__ __forceinline__ cd kz_root(double x, double y) {
-  double m = sqrt(x * x + y * y);
-  double t = sqrt(0.5 * (m + fabs(x)));
-  double o = (t > 0.0) ? 0.5 * (y / t) : 0.0;
-  cd pos = mk(t, o);
-  cd neg = mk(-o, -t);
-  return (x >= 0.0) ? pos : neg;
+// |w|^2 gets 1e-300 added, which changes nothing unless w = 0 exactly, where
+// it yields kz of order 1e-75 instead of 0 (and keeps every value finite).
+struct Root {
+  cd kz;
+  double inv_abs2;
+};
+__device__ __forceinline__ Root kz_root(double x, double y) {
+  const double a = fma(x, x, fma(y, y, 1e-300));
+  const double ra = rsq(a);
+  const double m = a * ra;
+  const double h = 0.5 * (m + fabs(x));
+  const double rh = rsq(h);
+  const double t = h * rh;
+  const double o = 0.5 * (y * rh);
+  Root out;
+  out.kz.re = (x >= 0.0) ? t : -o;
+  out.kz.im = (x >= 0.0) ? o : -t;
+  out.inv_abs2 = ra;
+  return out;
 }
 
 // Smearing node q = Q + ((dQ/Q) Q / (2 sqrt(2 ln 2))) t, in this order, no FMA.

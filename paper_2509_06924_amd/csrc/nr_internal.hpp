@@ -12,6 +12,9 @@ namespace nr {
 constexpr int kSmearNodes = NR_SMEAR_NODES;
 constexpr int kMaxLayers = NR_MAX_LAYERS;
 constexpr int kWuPoints = 64;  // data points per work unit (one per lane)
+// Deepest stack whose gradient kernel keeps the per-level state and phases
+// in LDS (3 x 16 B x 64 lanes per level); deeper stacks recompute them.
+constexpr int kStoreMaxLayers = 10;
 
 constexpr uint32_t kItemNonfinite = NR_ITEM_NONFINITE;
 constexpr uint32_t kItemBadQ = NR_ITEM_BAD_Q;
@@ -56,8 +59,9 @@ struct KernelArgs {
   // outputs
   double* out;  // nr_reflectivity
   double* rec;  // workspace records
-  // quadrature rule (device, plan-owned): node offsets in units of sigma_Q,
-  // then normalised weights, kSmearNodes each
+  // plan-owned constants (device): quadrature node offsets in units of
+  // sigma_Q and normalised weights (kSmearNodes each), then the tables
+  // (sin, cos)(k pi/32) for k = 0..63 interleaved and 2^(j/64), j = 0..63
   const double* rule;
 };
 

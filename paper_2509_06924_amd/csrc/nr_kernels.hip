@@ -6,19 +6,26 @@
 // points of its dataset, one wave (64 lanes) per WU, lane = data point.  The
 // item is wave-uniform, so its layer constants are staged once per wave in LDS
 // and read as broadcasts.  A lane walks all quadrature nodes of its point; for
-// each node it runs the layer product bottom-up (substrate -> surface) keeping
-// the two-component state of every level in registers, then the adjoint top
-// down, recomputing each layer's wavevector, interface coefficient and phase
-// instead of storing them.
+// each node it runs the layer product bottom-up (substrate -> surface), then
+// the adjoint top down, and accumulates w_k dR(q_k)/d(theta) in registers;
+// the point's likelihood seed multiplies the accumulators once at the end.
 //
 // The layer product is written in a scaled form: the Abeles column
 // v_j = C_j v_{j+1} is divided by E_j at every layer, which leaves r = v1/v0
 // unchanged and turns the phase factor into e_j = E_j^-2 = exp(-2 i kz_j d_j),
 // whose modulus is <= 1 on the chosen branch (Im kz <= 0):
 //   P <- P + r'_j Qv,   Qv <- e_j (r'_j P + Qv),   starting from (1, 0).
+//
+// Two gradient variants (one source, selected by template):
+//   store     - the forward sweep keeps each level's state (P, Qv) and phase
+//               e_j in LDS and each medium's kz_j, 1/|kz_j|^2 in registers;
+//               the adjoint recomputes only the interface coefficients.
+//   recompute - for deep stacks: the state tape stays in registers and the
+//               adjoint recomputes every layer's wavevector and phase.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "nr_device.hpp"
 #include "nr_internal.hpp"
@@ -33,21 +40,20 @@ namespace nr {
 //   C[j]  = -2 sigma_{j+1}^2                  (Nevot-Croce exponent factor)
 //   Nr/Ni[j] = w_j - w_{j+1} = (A[j+1]-A[j]) + i (B[j+1]-B[j]),
 //           the Q-independent numerator of r_j = (w_j - w_{j+1})/(kz_j + kz_{j+1})^2
+// plus the quadrature rule and the exp/sincos tables.
 // ---------------------------------------------------------------------------
 struct ItemConsts {
   double A[kMaxLayers + 2], B[kMaxLayers + 2], D[kMaxLayers + 2], C[kMaxLayers + 2],
       Nr[kMaxLayers + 2], Ni[kMaxLayers + 2];
-  // smearing rule: node offsets (units of sigma_Q) and weights
   double t[kSmearNodes], w[kSmearNodes];
+  MathTables tab;
 };
 
 // Reads of the staged constants are volatile so that the compiler re-reads
 // them from LDS at every use instead of keeping every layer's constants in
 // registers across the node loop.
 typedef __attribute__((address_space(3))) const volatile double lds_cv_double;
-__device__ __forceinline__ double ld(const double& x) {
-  return *(lds_cv_double*)(&x);
-}
+__device__ __forceinline__ double ld(const double& x) { return *(lds_cv_double*)(&x); }
 
 __device__ __forceinline__ void stage_item(ItemConsts& s, const double* rows, int N, int lane,
                                            const double* rule) {
@@ -67,6 +73,11 @@ __device__ __forceinline__ void stage_item(ItemConsts& s, const double* rows, in
     s.t[lane] = rule[lane];
     s.w[lane] = rule[kSmearNodes + lane];
   }
+  // tables follow the rule in the same device buffer
+  const double* tb = rule + 2 * kSmearNodes;
+  s.tab.sc[lane][0] = tb[2 * lane];
+  s.tab.sc[lane][1] = tb[2 * lane + 1];
+  s.tab.e2[lane] = tb[128 + lane];
   __syncthreads();
   if (lane <= N) {
     s.Nr[lane] = s.A[lane + 1] - s.A[lane];
@@ -84,21 +95,26 @@ struct Iface {
   cd kk;  // kz_j kz_{j+1}
 };
 
-__device__ __forceinline__ Iface interface_coeffs(cd kzc, cd kzn, double Nr, double Ni, double C) {
+__device__ __forceinline__ Iface interface_coeffs(const MathTables& T, cd kzc, cd kzn, double Nr,
+                                                  double Ni, double C) {
   Iface o;
   o.s = crecip(kzc + kzn);
-  cd s2 = o.s * o.s;
+  const cd s2 = o.s * o.s;
   // identical media: r = 0 exactly (also avoids 0 * inf when both kz vanish)
   o.r = (Nr == 0.0 && Ni == 0.0) ? mk(0.0, 0.0) : mk(Nr, Ni) * s2;
   o.kk = kzc * kzn;
-  o.f = cexp(C * o.kk);
+  o.f = cexp_tab(T, C * o.kk);
   o.rp = o.r * o.f;
   return o;
 }
 
 // e_j = exp(-2 i kz_j d_j) = exp(D Im kz) cis(-D Re kz), D = 2 d_j.
-__device__ __forceinline__ cd layer_phase(cd kz, double D) {
-  return cexp(mk(D * kz.im, -D * kz.re));
+__device__ __forceinline__ cd layer_phase(const MathTables& T, cd kz, double D) {
+  return cexp_tab(T, mk(D * kz.im, -D * kz.re));
+}
+
+__device__ __forceinline__ Root medium_root(const ItemConsts& s, double kz0sq, int m) {
+  return kz_root(kz_real_part(kz0sq, ld(s.A[m])), -ld(s.B[m]));
 }
 
 // ---------------------------------------------------------------------------
@@ -106,25 +122,25 @@ __device__ __forceinline__ cd layer_phase(cd kz, double D) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double node_reflectivity(const ItemConsts& s, int N, double q) {
   const double kz0sq = kz0_squared(q);
-  cd kzn = kz_root(kz_real_part(kz0sq, ld(s.A[N + 1])), -ld(s.B[N + 1]));
+  cd kzn = medium_root(s, kz0sq, N + 1).kz;
   cd P = mk(1.0, 0.0), Qv = mk(0.0, 0.0);
   for (int jj = N; jj >= 1; --jj) {
-    cd kzc = kz_root(kz_real_part(kz0sq, ld(s.A[jj])), -ld(s.B[jj]));
-    Iface it = interface_coeffs(kzc, kzn, ld(s.Nr[jj]), ld(s.Ni[jj]), ld(s.C[jj]));
-    cd Pn = P + it.rp * Qv;
-    cd t = it.rp * P + Qv;
-    Qv = layer_phase(kzc, ld(s.D[jj])) * t;
+    const cd kzc = medium_root(s, kz0sq, jj).kz;
+    const Iface it = interface_coeffs(s.tab, kzc, kzn, ld(s.Nr[jj]), ld(s.Ni[jj]), ld(s.C[jj]));
+    const cd Pn = P + it.rp * Qv;
+    const cd t = it.rp * P + Qv;
+    Qv = layer_phase(s.tab, kzc, ld(s.D[jj])) * t;
     P = Pn;
     kzn = kzc;
   }
   {
-    Iface it = interface_coeffs(mk(0.5 * q, 0.0), kzn, ld(s.Nr[0]), ld(s.Ni[0]), ld(s.C[0]));
-    cd Pn = P + it.rp * Qv;
+    const Iface it =
+        interface_coeffs(s.tab, mk(0.5 * q, 0.0), kzn, ld(s.Nr[0]), ld(s.Ni[0]), ld(s.C[0]));
+    const cd Pn = P + it.rp * Qv;
     Qv = it.rp * P + Qv;
     P = Pn;
   }
-  cd r = Qv * crecip(P);
-  return cabs2(r);
+  return cabs2(Qv * crecip(P));
 }
 
 // Shared WU prologue.
@@ -153,7 +169,8 @@ __device__ __forceinline__ WuInfo wu_setup(const KernelArgs& a, int w, int lane)
 }
 
 __device__ __forceinline__ void flag(int32_t* status, int item, uint32_t bits) {
-  if (status != nullptr && bits != 0u) atomicOr(reinterpret_cast<unsigned int*>(status + item), bits);
+  if (status != nullptr && bits != 0u)
+    atomicOr(reinterpret_cast<unsigned int*>(status + item), bits);
 }
 
 // ---------------------------------------------------------------------------
@@ -163,7 +180,7 @@ __global__ __launch_bounds__(64) void k_reflectivity(KernelArgs a) {
   __shared__ ItemConsts s;
   const int lane = threadIdx.x;
   const int w = blockIdx.x;
-  WuInfo u = wu_setup(a, w, lane);
+  const WuInfo u = wu_setup(a, w, lane);
   stage_item(s, a.layers + 4 * u.roff, u.N, lane, a.rule);
   const int K = (u.dqq > 0.0) ? kSmearNodes : 1;
   double Rsm = 0.0;
@@ -206,7 +223,7 @@ __global__ __launch_bounds__(64) void k_loglik(KernelArgs a) {
   __shared__ ItemConsts s;
   const int lane = threadIdx.x;
   const int w = blockIdx.x;
-  WuInfo u = wu_setup(a, w, lane);
+  const WuInfo u = wu_setup(a, w, lane);
   stage_item(s, a.layers + 4 * u.roff, u.N, lane, a.rule);
   const int K = (u.dqq > 0.0) ? kSmearNodes : 1;
   double Rsm = 0.0;
@@ -229,6 +246,218 @@ __global__ __launch_bounds__(64) void k_loglik(KernelArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint of one interface/layer step (shared by both gradient variants).
+// In: state (Ps, Qs) entering level j (= state of level j+1), cotangents
+// (Pb, Qb) of the state leaving level j, kz_j, kz_{j+1}, the interface
+// coefficients, the phase e_j (j >= 1).  Out: cotangents of the state entering
+// the level, kzbar contributions, and the d / sigma accumulators.
+// ---------------------------------------------------------------------------
+struct AdjStep {
+  cd Pb, Qb;   // cotangents of the state entering level j
+  cd kzb_c;    // contribution to kzbar_j
+  cd kzb_n;    // contribution to kzbar_{j+1}
+  double dd;   // dl/dd_j
+  double ss;   // Re(conj(ubar) kz_j kz_{j+1})  (times -4 sigma_{j+1} later)
+};
+
+__device__ __forceinline__ AdjStep adjoint_step(cd Ps, cd Qs, cd Pb, cd Qb, cd kzc, cd kzn,
+                                                const Iface& it, double C, bool has_phase, cd e,
+                                                double D) {
+  AdjStep o;
+  const cd t = it.rp * Ps + Qs;
+  cd tb, eb = mk(0.0, 0.0);
+  if (has_phase) {
+    eb = cmulc(t, Qb);
+    tb = cmulc(e, Qb);
+  } else {
+    tb = Qb;
+  }
+  // P_new = P + r' Qv ; t = r' P + Qv
+  const cd rpb = cmulc(Qs, Pb) + cmulc(Ps, tb);
+  o.Pb = Pb + cmulc(it.rp, tb);
+  o.Qb = cmulc(it.rp, Pb) + tb;
+  // r' = r f, f = exp(C kz_j kz_{j+1})
+  const cd rb = cmulc(it.f, rpb);
+  const cd ub = cmulc(it.rp, rpb);
+  o.ss = ub.re * it.kk.re + ub.im * it.kk.im;
+  // r = (kz_j - kz_{j+1}) s: dr/dkz_j = 2 kz_{j+1} s^2, dr/dkz_{j+1} = -2 kz_j s^2
+  const cd s2 = it.s * it.s;
+  o.kzb_c = cmulc(C * kzn, ub) + cmulc(2.0 * (kzn * s2), rb);
+  o.kzb_n = cmulc(C * kzc, ub) + cmulc(-2.0 * (kzc * s2), rb);
+  o.dd = 0.0;
+  if (has_phase) {
+    // e = exp(-2 i kz d): de/dkz = -i D e, de/dd = -2 i kz e
+    o.kzb_c += cmulc(mk(D * e.im, -D * e.re), eb);
+    const cd ze = kzc * e;
+    o.dd = eb.re * (2.0 * ze.im) + eb.im * (-2.0 * ze.re);
+  }
+  return o;
+}
+
+// wbar = conj(dkz/dw) kzbar = conj(1/(2 kz)) kzbar = kz kzbar / (2 |kz|^2)
+__device__ __forceinline__ cd wbar_of(cd kz, double inv_abs2, cd kzb) {
+  return (0.5 * inv_abs2) * (kz * kzb);
+}
+
+// Per-lane gradient accumulators for one point: sum_k w_k dR(q_k)/d(.)
+template <int LMAX>
+struct Accum {
+  cd Hw[LMAX + 2];
+  double Hd[LMAX + 2], Hs[LMAX + 2];
+};
+
+template <int LMAX>
+struct GradTape {
+  // per-lane state entering each level and the layer phase, lane-minor
+  double2 P[LMAX + 1][64], Qv[LMAX + 1][64], E[LMAX + 1][64];
+};
+
+__device__ __forceinline__ double2 to_d2(cd z) { return make_double2(z.re, z.im); }
+__device__ __forceinline__ cd from_d2(double2 v) { return mk(v.x, v.y); }
+
+// ---------------------------------------------------------------------------
+// One node, store variant: forward with the tape in LDS and kz in registers,
+// then the adjoint.  Returns R(q) and adds w_k dR/d(.) to the accumulators.
+// ---------------------------------------------------------------------------
+template <int LMAX>
+__device__ __forceinline__ double node_grad_store(const ItemConsts& s, GradTape<LMAX>& tp,
+                                                  Accum<LMAX>& acc, int N, int lane, double q,
+                                                  double wk) {
+  const double kz0sq = kz0_squared(q);
+  cd kz[LMAX + 2];
+  double ia[LMAX + 2];
+  Iface ifc[LMAX + 1];
+  cd P = mk(1.0, 0.0), Qv = mk(0.0, 0.0);
+#pragma unroll
+  for (int jj = LMAX + 1; jj >= 0; --jj) {
+    if (jj == N + 1) {
+      const Root rt = medium_root(s, kz0sq, jj);
+      kz[jj] = rt.kz;
+      ia[jj] = rt.inv_abs2;
+    } else if (jj <= N) {
+      if (jj == 0) {
+        kz[0] = mk(0.5 * q, 0.0);
+        ia[0] = 0.0;
+      } else {
+        const Root rt = medium_root(s, kz0sq, jj);
+        kz[jj] = rt.kz;
+        ia[jj] = rt.inv_abs2;
+      }
+      const Iface it =
+          interface_coeffs(s.tab, kz[jj], kz[jj + 1], ld(s.Nr[jj]), ld(s.Ni[jj]), ld(s.C[jj]));
+      ifc[jj] = it;
+      tp.P[jj][lane] = to_d2(P);
+      tp.Qv[jj][lane] = to_d2(Qv);
+      const cd Pn = P + it.rp * Qv;
+      const cd t = it.rp * P + Qv;
+      if (jj >= 1) {
+        const cd e = layer_phase(s.tab, kz[jj], ld(s.D[jj]));
+        tp.E[jj][lane] = to_d2(e);
+        Qv = e * t;
+      } else {
+        Qv = t;
+      }
+      P = Pn;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  const cd iP = crecip(P);
+  const cd r = Qv * iP;
+  const cd rbar = (2.0 * wk) * r;
+  cd Pb = cmulc(-(r * iP), rbar);  // conj(dr/dP) rbar, dr/dP = -r/P
+  cd Qb = cmulc(iP, rbar);         // conj(dr/dQv) rbar, dr/dQv = 1/P
+  cd kzbc = mk(0.0, 0.0);
+#pragma unroll
+  for (int jj = 0; jj <= LMAX; ++jj) {
+    if (jj <= N) {
+      const double C = ld(s.C[jj]);
+      const Iface& it = ifc[jj];
+      const cd Ps = from_d2(tp.P[jj][lane]);
+      const cd Qs = from_d2(tp.Qv[jj][lane]);
+      const bool ph = jj >= 1;
+      const cd e = ph ? from_d2(tp.E[jj][lane]) : mk(1.0, 0.0);
+      const AdjStep st =
+          adjoint_step(Ps, Qs, Pb, Qb, kz[jj], kz[jj + 1], it, C, ph, e, ph ? ld(s.D[jj]) : 0.0);
+      kzbc += st.kzb_c;
+      acc.Hs[jj + 1] += st.ss;
+      if (ph) {
+        acc.Hd[jj] += st.dd;
+        acc.Hw[jj] += wbar_of(kz[jj], ia[jj], kzbc);
+      }
+      if (jj == N) acc.Hw[jj + 1] += wbar_of(kz[jj + 1], ia[jj + 1], st.kzb_n);
+      Pb = st.Pb;
+      Qb = st.Qb;
+      kzbc = st.kzb_n;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  return cabs2(r);
+}
+
+// ---------------------------------------------------------------------------
+// One node, recompute variant: the state tape stays in registers; the adjoint
+// recomputes each medium's wavevector and each layer's phase.
+// ---------------------------------------------------------------------------
+template <int LMAX>
+__device__ __forceinline__ double node_grad_recompute(const ItemConsts& s, Accum<LMAX>& acc, int N,
+                                                      double q, double wk) {
+  const double kz0sq = kz0_squared(q);
+  const cd kz0 = mk(0.5 * q, 0.0);
+  cd tapeP[LMAX + 1], tapeQ[LMAX + 1];
+  cd kzn = medium_root(s, kz0sq, N + 1).kz;
+  cd P = mk(1.0, 0.0), Qv = mk(0.0, 0.0);
+#pragma unroll
+  for (int jj = LMAX; jj >= 0; --jj) {
+    if (jj <= N) {
+      const cd kzc = (jj == 0) ? kz0 : medium_root(s, kz0sq, jj).kz;
+      tapeP[jj] = P;
+      tapeQ[jj] = Qv;
+      const Iface it = interface_coeffs(s.tab, kzc, kzn, ld(s.Nr[jj]), ld(s.Ni[jj]), ld(s.C[jj]));
+      const cd Pn = P + it.rp * Qv;
+      const cd t = it.rp * P + Qv;
+      Qv = (jj >= 1) ? layer_phase(s.tab, kzc, ld(s.D[jj])) * t : t;
+      P = Pn;
+      kzn = kzc;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  const cd iP = crecip(P);
+  const cd r = Qv * iP;
+  const cd rbar = (2.0 * wk) * r;
+  cd Pb = cmulc(-(r * iP), rbar);
+  cd Qb = cmulc(iP, rbar);
+  cd kzc = kz0;
+  double iac = 0.0;
+  cd kzbc = mk(0.0, 0.0);
+#pragma unroll
+  for (int jj = 0; jj <= LMAX; ++jj) {
+    if (jj <= N) {
+      const Root rn = medium_root(s, kz0sq, jj + 1);
+      const double C = ld(s.C[jj]);
+      const Iface it = interface_coeffs(s.tab, kzc, rn.kz, ld(s.Nr[jj]), ld(s.Ni[jj]), C);
+      const bool ph = jj >= 1;
+      const double D = ph ? ld(s.D[jj]) : 0.0;
+      const cd e = ph ? layer_phase(s.tab, kzc, D) : mk(1.0, 0.0);
+      const AdjStep st = adjoint_step(tapeP[jj], tapeQ[jj], Pb, Qb, kzc, rn.kz, it, C, ph, e, D);
+      kzbc += st.kzb_c;
+      acc.Hs[jj + 1] += st.ss;
+      if (ph) {
+        acc.Hd[jj] += st.dd;
+        acc.Hw[jj] += wbar_of(kzc, iac, kzbc);
+      }
+      if (jj == N) acc.Hw[jj + 1] += wbar_of(rn.kz, rn.inv_abs2, st.kzb_n);
+      Pb = st.Pb;
+      Qb = st.Qb;
+      kzc = rn.kz;
+      iac = rn.inv_abs2;
+      kzbc = st.kzb_n;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  return cabs2(r);
+}
+
+// ---------------------------------------------------------------------------
 // logL + gradient partials per WU (nr_loglik_grad).
 // Record layout (NR = N + 2 media):
 //   [0] logL, [1] d/dscale, [2] d/dbkg,
@@ -237,26 +466,25 @@ __global__ __launch_bounds__(64) void k_loglik(KernelArgs a) {
 //   [3 + 2NR + m]  sum dl/dd_m
 //   [3 + 3NR + m]  sum Re(conj(ubar) kz_{m-1} kz_m)   (sigma_m factor applied later)
 // ---------------------------------------------------------------------------
-template <int LMAX>
+template <int LMAX, bool STORE>
 __global__ __launch_bounds__(64) void k_loglik_grad(KernelArgs a) {
   __shared__ ItemConsts s;
+  using Tape = typename std::conditional<STORE, GradTape<LMAX>, char>::type;
+  __shared__ Tape tape;
   const int lane = threadIdx.x;
   const int w = blockIdx.x;
-  WuInfo u = wu_setup(a, w, lane);
+  const WuInfo u = wu_setup(a, w, lane);
   stage_item(s, a.layers + 4 * u.roff, u.N, lane, a.rule);
   const int N = u.N;
   const int K = (u.dqq > 0.0) ? kSmearNodes : 1;
 
-  // per-lane accumulators of sum_k w_k dR(q_k)/d(.)
-  cd Hw[LMAX + 2];
-  double Hd[LMAX + 2], Hs[LMAX + 2];
+  Accum<LMAX> acc;
 #pragma unroll
   for (int m = 0; m < LMAX + 2; ++m) {
-    Hw[m] = mk(0.0, 0.0);
-    Hd[m] = 0.0;
-    Hs[m] = 0.0;
+    acc.Hw[m] = mk(0.0, 0.0);
+    acc.Hd[m] = 0.0;
+    acc.Hs[m] = 0.0;
   }
-  cd tapeP[LMAX + 1], tapeQ[LMAX + 1];
 
   double Rsm = 0.0;
   bool badq = !(u.Q > 0.0);
@@ -264,85 +492,12 @@ __global__ __launch_bounds__(64) void k_loglik_grad(KernelArgs a) {
     const double q = (K == 1) ? u.Q : smear_node(u.Q, u.dqq, ld(s.t[k]));
     badq |= !(q > 0.0);
     const double wk = (K == 1) ? 1.0 : ld(s.w[k]);
-    const double kz0sq = kz0_squared(q);
-    const cd kz0 = mk(0.5 * q, 0.0);
-
-    // ---- forward, bottom-up, recording the state entering each level ----
-    cd kzn = kz_root(kz_real_part(kz0sq, ld(s.A[N + 1])), -ld(s.B[N + 1]));
-    cd P = mk(1.0, 0.0), Qv = mk(0.0, 0.0);
-#pragma unroll
-    for (int jj = LMAX; jj >= 0; --jj) {
-      if (jj <= N) {
-        cd kzc = (jj == 0) ? kz0 : kz_root(kz_real_part(kz0sq, ld(s.A[jj])), -ld(s.B[jj]));
-        tapeP[jj] = P;
-        tapeQ[jj] = Qv;
-        Iface it = interface_coeffs(kzc, kzn, ld(s.Nr[jj]), ld(s.Ni[jj]), ld(s.C[jj]));
-        cd Pn = P + it.rp * Qv;
-        cd t = it.rp * P + Qv;
-        Qv = (jj >= 1) ? layer_phase(kzc, ld(s.D[jj])) * t : t;
-        P = Pn;
-        kzn = kzc;
-      }
-      // keep the scheduler from hoisting later layers' work (register pressure)
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    const cd iP = crecip(P);
-    const cd r = Qv * iP;
-    Rsm += wk * cabs2(r);
-
-    // ---- adjoint, top-down: l = w_k |r|^2 ----
-    const cd rbar = (2.0 * wk) * r;
-    cd Pb = cmulc(-(r * iP), rbar);  // conj(dr/dP) rbar, dr/dP = -r/P
-    cd Qb = cmulc(iP, rbar);         // conj(dr/dQv) rbar, dr/dQv = 1/P
-    cd kzc = kz0;
-    cd kzbc = mk(0.0, 0.0);
-#pragma unroll
-    for (int jj = 0; jj <= LMAX; ++jj) {
-      if (jj <= N) {
-        cd kzn2 = kz_root(kz_real_part(kz0sq, ld(s.A[jj + 1])), -ld(s.B[jj + 1]));
-        Iface it = interface_coeffs(kzc, kzn2, ld(s.Nr[jj]), ld(s.Ni[jj]), ld(s.C[jj]));
-        const cd Ps = tapeP[jj], Qs = tapeQ[jj];
-        const cd t = it.rp * Ps + Qs;
-        cd tb;
-        cd e = mk(1.0, 0.0), eb = mk(0.0, 0.0);
-        if (jj >= 1) {
-          e = layer_phase(kzc, ld(s.D[jj]));
-          eb = cmulc(t, Qb);
-          tb = cmulc(e, Qb);
-        } else {
-          tb = Qb;
-        }
-        // P_new = P + r' Qv ; t = r' P + Qv
-        const cd rpb = cmulc(Qs, Pb) + cmulc(Ps, tb);
-        const cd Pb_new = Pb + cmulc(it.rp, tb);
-        const cd Qb_new = cmulc(it.rp, Pb) + tb;
-        // r' = r f, f = exp(C kz_j kz_{j+1})
-        const cd rb = cmulc(it.f, rpb);
-        const cd ub = cmulc(it.rp, rpb);
-        kzbc += cmulc(ld(s.C[jj]) * kzn2, ub);
-        cd kzbn = cmulc(ld(s.C[jj]) * kzc, ub);
-        Hs[jj + 1] += ub.re * it.kk.re + ub.im * it.kk.im;
-        // r = (kz_j - kz_{j+1}) s: dr/dkz_j = 2 kz_{j+1} s^2, dr/dkz_{j+1} = -2 kz_j s^2
-        const cd s2 = it.s * it.s;
-        kzbc += cmulc(2.0 * (kzn2 * s2), rb);
-        kzbn += cmulc(-2.0 * (kzc * s2), rb);
-        if (jj >= 1) {
-          // e = exp(-2 i kz d): de/dkz = -i D e, de/dd = -2 i kz e
-          const double D = ld(s.D[jj]);
-          kzbc += cmulc(mk(D * e.im, -D * e.re), eb);
-          const cd ze = kzc * e;
-          Hd[jj] += eb.re * (2.0 * ze.im) + eb.im * (-2.0 * ze.re);
-          // w_j = kz_j^2: wbar = conj(1/(2 kz_j)) kzbar
-          Hw[jj] += cmulc(crecip(2.0 * kzc), kzbc);
-        }
-        if (jj == N) Hw[jj + 1] += cmulc(crecip(2.0 * kzn2), kzbn);
-        Pb = Pb_new;
-        Qb = Qb_new;
-        kzc = kzn2;
-        kzbc = kzbn;
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    }
+    double R;
+    if constexpr (STORE)
+      R = node_grad_store<LMAX>(s, tape, acc, N, lane, q, wk);
+    else
+      R = node_grad_recompute<LMAX>(s, acc, N, q, wk);
+    Rsm += wk * R;
   }
 
   // ---- instrument, likelihood, seeds ----
@@ -374,10 +529,10 @@ __global__ __launch_bounds__(64) void k_loglik_grad(KernelArgs a) {
 #pragma unroll
   for (int m = 0; m < LMAX + 2; ++m) {
     if (m < NR) {
-      const double wr = wave_sum(fac * Hw[m].re);
-      const double wi = wave_sum(fac * Hw[m].im);
-      const double dd = wave_sum(fac * Hd[m]);
-      const double ss = wave_sum(fac * Hs[m]);
+      const double wr = wave_sum(fac * acc.Hw[m].re);
+      const double wi = wave_sum(fac * acc.Hw[m].im);
+      const double dd = wave_sum(fac * acc.Hd[m]);
+      const double ss = wave_sum(fac * acc.Hs[m]);
       if (lane == 0) {
         rec[3 + m] = wr;
         rec[3 + NR + m] = wi;
@@ -463,9 +618,10 @@ hipError_t launch_forward(int op, const KernelArgs& a, int n_wu, hipStream_t st)
 hipError_t launch_grad(int bucket, const KernelArgs& a, int n_wu, hipStream_t st) {
   if (n_wu <= 0) return hipSuccess;
   switch (kBucketLmax[bucket]) {
-#define NR_CASE(LM)                                                                   \
-  case LM:                                                                            \
-    hipLaunchKernelGGL(k_loglik_grad<LM>, dim3(n_wu), dim3(64), 0, st, a);            \
+#define NR_CASE(LM)                                                                         \
+  case LM:                                                                                  \
+    hipLaunchKernelGGL((k_loglik_grad<LM, (LM <= kStoreMaxLayers)>), dim3(n_wu), dim3(64), 0, \
+                       st, a);                                                              \
     return hipGetLastError();
     NR_BUCKETS(NR_CASE)
 #undef NR_CASE
