@@ -32,10 +32,10 @@ UNIT = "layer-steps/s"
 FP64_VALU_PEAK = 78.6e12  # MI355X dense FP64 vector, FLOP/s
 
 # Algorithmic FP64 operations per layer-step of the forward + reverse sweep
-# (operation count of the method; special functions at fixed costs:
+# (operation count of the method; FMA = 2; special functions at fixed costs:
 #  sqrt 10, divide 10, exp 20, sin+cos 40).  Derivation in the design doc.
 FLOP_FWD_PER_LAYER_STEP = 257
-FLOP_ADJ_PER_LAYER_STEP = 175
+FLOP_ADJ_PER_LAYER_STEP = 167
 FLOP_PER_LAYER_STEP = FLOP_FWD_PER_LAYER_STEP + FLOP_ADJ_PER_LAYER_STEP
 
 
@@ -129,6 +129,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra-rows", action="store_true",
+                    help="skip the forward-only and per-item (unbatched) rows")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=float, default=0.0,
                     help="only run a plain device copy of this size (counter calibration)")
@@ -223,9 +225,48 @@ def main():
             "flop_per_layer_step": FLOP_PER_LAYER_STEP,
         },
     }
+    if not args.no_extra_rows:
+        rec["forward_only"] = forward_only_row(prob, batch, args.steps)
+        rec["plain_unbatched"] = plain_unbatched_row(nr, batch)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
     print(json.dumps(rec), flush=True)
+
+
+def forward_only_row(prob, batch, steps):
+    """The same workload through nr_loglik (value only, no adjoint)."""
+    import torch
+    for _ in range(2):
+        prob.loglik()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        prob.loglik()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {"value": batch.layer_steps() / dt, "unit": UNIT, "ms_per_step": dt * 1e3,
+            "what": "nr_loglik on the same batch (forward only)"}
+
+
+def plain_unbatched_row(nr, batch, n_items=64):
+    """The same kernels launched once per item (batch of 1), host loop, no
+    graph: what a per-evaluation call pattern gets on this GPU."""
+    import numpy as np
+    import torch
+    items = np.arange(min(n_items, batch.n_items))
+    probs = [nr.Problem.from_batch(batch.subset([int(b)]), device="cuda:0") for b in items]
+    for p in probs:
+        p.loglik_grad()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in probs:
+        p.loglik_grad()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ls = batch.subset(items).layer_steps()
+    return {"value": ls / dt, "unit": UNIT, "items": int(items.size),
+            "ms_per_item": dt / items.size * 1e3,
+            "what": "nr_loglik_grad per item, batch of 1, host loop"}
 
 
 if __name__ == "__main__":

@@ -125,8 +125,12 @@ nr_status nr_plan_create(const nr_batch_desc* desc, nr_plan** plan_out);
 /* Releases a plan and its device memory.  NULL is accepted. */
 nr_status nr_plan_destroy(nr_plan* plan);
 
-/* Bytes of caller-provided device workspace that `op` needs for this plan
- * (0 is possible).  Returns NR_EINVAL for an unknown op or a NULL plan. */
+/* Bytes of caller-provided device workspace that `op` needs for this plan:
+ * 48 bytes per row of every item (per-layer constants) plus, for NR_OP_LOGLIK
+ * and NR_OP_LOGLIK_GRAD, the per-work-unit partial sums.  Any 8-byte aligned
+ * device buffer of at least that size; contents need no initialisation and
+ * are overwritten by every call.  Returns NR_EINVAL for an unknown op or a
+ * NULL plan. */
 nr_status nr_workspace_size(const nr_plan* plan, int32_t op, size_t* bytes);
 
 /* Packed output offsets: R_hat of item b starts at element out_off[b] of the
@@ -135,7 +139,7 @@ nr_status nr_output_offsets(const nr_plan* plan, int64_t* out_off);
 
 /* Model curve (Abeles + smearing + instrument, Sec. 2.1 / Sec. 3): writes
  * R_hat for every point of every item into device r_hat[out_off[n_items]],
- * item-major, in the dataset's point order.  Needs no workspace. */
+ * item-major, in the dataset's point order. */
 nr_status nr_reflectivity(const nr_plan* plan, const nr_values* v, double* r_hat,
                           void* workspace, size_t workspace_bytes, void* stream);
 

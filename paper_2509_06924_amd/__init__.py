@@ -158,7 +158,8 @@ class Problem:
     def reflectivity(self, layers=None, scale=None, bkg=None, stream=None):
         import torch
         out = torch.empty(int(self.out_off[-1]), dtype=torch.float64, device=self.device)
-        nr_reflectivity(self.plan, self.values(layers, scale, bkg), out, None, stream)
+        nr_reflectivity(self.plan, self.values(layers, scale, bkg), out,
+                        self.workspace(NR_OP_REFLECTIVITY), stream)
         return out
 
     def loglik(self, layers=None, scale=None, bkg=None, stream=None):

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -85,13 +86,26 @@ void append_math_tables(std::vector<double>& v) {
   for (int j = 0; j < 64; ++j) v.push_back((double)std::exp2((long double)j / 64.0L));
 }
 
+// One kernel launch: a work list for one layer-count bucket.  Full units
+// cover 64 consecutive points of one item; tail units pack the trailing
+// partial groups of several items of equal depth, lane by lane.
 struct Launch {
   int bucket = 0;
+  bool tail = false;
   int n_wu = 0;
-  int32_t* item = nullptr;
-  int32_t* p0 = nullptr;
-  int64_t* rec_grad = nullptr;
-  int64_t* rec_ll = nullptr;
+  int32_t* item = nullptr;      // [n_wu]: the unit's item (first item for tails)
+  int32_t* p0 = nullptr;        // [n_wu]: first point (full units)
+  int64_t* rec = nullptr;       // [n_wu]: record offset (full units)
+  int32_t* lane_item = nullptr; // [n_wu * 64] (tail units)
+  int32_t* lane_pt = nullptr;   // [n_wu * 64]
+  int64_t* lane_rec = nullptr;  // [n_wu * 64], -1 for idle lanes
+};
+
+// Per-item lists of record offsets summed by the reduction kernels.
+struct RecordLists {
+  int64_t* first = nullptr;
+  int32_t* count = nullptr;
+  int64_t* offs = nullptr;
 };
 
 template <class T>
@@ -111,20 +125,17 @@ struct nr_plan {
   std::vector<int64_t> q_off, row_off, out_off;
   std::vector<int32_t> dataset_of_item;
   std::vector<double> dqq;
-  int64_t n_wu_total = 0, rec_grad_total = 0;
+  int64_t rec_ll_total = 0, rec_grad_total = 0;
   // device copies
   int32_t* d_dataset_of_item = nullptr;
   int64_t* d_q_off = nullptr;
   int64_t* d_row_off = nullptr;
   double* d_dqq = nullptr;
   int64_t* d_out_off = nullptr;
-  int64_t* d_item_wu_first = nullptr;
-  int32_t* d_item_wu_count = nullptr;
-  int64_t* d_rec_of_wu_grad = nullptr;
-  int64_t* d_rec_of_wu_ll = nullptr;
+  RecordLists lists_ll, lists_grad;
   double* d_rule = nullptr;
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;
-  std::vector<Launch> launches;
+  std::vector<Launch> launches_fwd, launches_grad;
   double node_t[kSmearNodes], node_w[kSmearNodes];
   std::vector<void*> owned;
 };
@@ -192,17 +203,37 @@ KernelArgs base_args(const nr_plan* p, const nr_values* v) {
   return a;
 }
 
+// Workspace layout: per-row layer records (6 doubles per row of every item),
+// then the per-work-unit partial records of the operation.
+size_t consts_doubles(const nr_plan* p) { return (size_t)p->row_off.back() * 6; }
+
+size_t op_doubles(const nr_plan* p, int op) {
+  size_t n = consts_doubles(p);
+  if (op == NR_OP_LOGLIK) n += (size_t)p->rec_ll_total;
+  if (op == NR_OP_LOGLIK_GRAD) n += (size_t)p->rec_grad_total;
+  return n;
+}
+
 nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st) {
+  {
+    hipError_t e = launch_item_consts(p->d_row_off, a.layers, const_cast<double*>(a.consts),
+                                      p->n_items, st);
+    if (e != hipSuccess) return hip_fail(e, "constants launch");
+  }
   if (p->ev_start) {
     hipError_t e = hipEventRecord(p->ev_start, st);
     if (e != hipSuccess) return hip_fail(e, "timing event");
   }
-  for (const Launch& L : p->launches) {
+  const bool grad = (op == kOpLoglikGrad);
+  for (const Launch& L : grad ? p->launches_grad : p->launches_fwd) {
     a.wu_item = L.item;
     a.wu_p0 = L.p0;
-    a.wu_rec = (op == kOpLoglikGrad) ? L.rec_grad : L.rec_ll;
-    hipError_t e = (op == kOpLoglikGrad) ? launch_grad(L.bucket, a, L.n_wu, st)
-                                         : launch_forward(op, a, L.n_wu, st);
+    a.wu_rec = L.rec;
+    a.tail_item = L.lane_item;
+    a.tail_pt = L.lane_pt;
+    a.tail_rec = L.lane_rec;
+    hipError_t e = grad ? launch_grad(L.bucket, L.tail, a, L.n_wu, st)
+                        : launch_forward(op, a, L.n_wu, st);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
   }
   if (p->ev_stop) {
@@ -254,40 +285,64 @@ nr_status nr_plan_create(const nr_batch_desc* d, nr_plan** out) {
   p->dqq.assign(d->dq_over_q, d->dq_over_q + d->n_datasets);
   smearing_rule(p->node_t, p->node_w);
 
-  // work units, item-major numbering
+  // ---- work lists -------------------------------------------------------
+  // Forward ops: one unit per item x 64 points (the last may be partial),
+  // one record (a logL partial) per unit.  Gradient op: full units as above
+  // plus tail units that pack the trailing partial groups of items with the
+  // same depth and node count; a full unit writes one record, a tail lane
+  // writes its own.  Every item's records are listed contiguously.
   const int nI = d->n_items;
-  std::vector<int64_t> item_wu_first(nI), rec_of_wu_grad, rec_of_wu_ll;
-  std::vector<int32_t> item_wu_count(nI);
   p->out_off.assign(nI + 1, 0);
   struct Wu {
     int32_t item, p0;
-    int64_t g;
+    int64_t rec;
     double cost;
   };
-  std::vector<std::vector<Wu>> per_bucket(kNumBuckets);
-  int64_t g = 0, rec = 0;
+  struct Tail {
+    int32_t item, p0, count;
+    int64_t rec0;  // record of its first point
+  };
+  std::vector<std::vector<Wu>> fwd_units(kNumBuckets), grad_units(kNumBuckets);
+  std::map<std::pair<int, int>, std::vector<Tail>> tails;  // (depth, nodes)
+  std::vector<int64_t> ll_first(nI), ll_offs, gr_first(nI), gr_offs;
+  std::vector<int32_t> ll_count(nI), gr_count(nI);
+  int64_t rec_ll = 0, rec_gr = 0;
   for (int b = 0; b < nI; ++b) {
     const int s = p->dataset_of_item[b];
     const int64_t nq = p->q_off[s + 1] - p->q_off[s];
     const int N = (int)(p->row_off[b + 1] - p->row_off[b]) - 2;
     const int K = p->dqq[s] > 0.0 ? kSmearNodes : 1;
-    const int nwu = (int)((nq + kWuPoints - 1) / kWuPoints);
     const int bk = bucket_of(N);
-    item_wu_first[b] = g;
-    item_wu_count[b] = nwu;
+    const int64_t rsz = 3 + 4 * (N + 2);
     p->out_off[b + 1] = p->out_off[b] + nq;
+    const int nwu = (int)((nq + kWuPoints - 1) / kWuPoints);
+    ll_first[b] = (int64_t)ll_offs.size();
+    ll_count[b] = nwu;
     for (int k = 0; k < nwu; ++k) {
       const int p0 = k * kWuPoints;
       const double pts = (double)std::min<int64_t>(kWuPoints, nq - p0);
-      per_bucket[bk].push_back({b, p0, g, pts * K * (N + 1)});
-      rec_of_wu_grad.push_back(rec);
-      rec_of_wu_ll.push_back(g);
-      rec += 3 + 4 * (N + 2);
-      ++g;
+      fwd_units[bk].push_back({b, p0, rec_ll, pts * K * (N + 1)});
+      ll_offs.push_back(rec_ll++);
+    }
+    const int nfull = (int)(nq / kWuPoints);
+    const int ntail = (int)(nq % kWuPoints);
+    gr_first[b] = (int64_t)gr_offs.size();
+    gr_count[b] = nfull + ntail;
+    for (int k = 0; k < nfull; ++k) {
+      grad_units[bk].push_back({b, k * kWuPoints, rec_gr, (double)kWuPoints * K * (N + 1)});
+      gr_offs.push_back(rec_gr);
+      rec_gr += rsz;
+    }
+    if (ntail > 0) {
+      tails[{N, K}].push_back({b, nfull * kWuPoints, ntail, rec_gr});
+      for (int t = 0; t < ntail; ++t) {
+        gr_offs.push_back(rec_gr);
+        rec_gr += rsz;
+      }
     }
   }
-  p->n_wu_total = g;
-  p->rec_grad_total = rec;
+  p->rec_ll_total = rec_ll;
+  p->rec_grad_total = rec_gr;
 
   hipError_t e = hipSuccess;
   auto keep = [&](void* ptr) { p->owned.push_back(ptr); };
@@ -297,10 +352,14 @@ nr_status nr_plan_create(const nr_batch_desc* d, nr_plan** out) {
   if (e == hipSuccess) { e = upload(&p->d_row_off, p->row_off); keep(p->d_row_off); }
   if (e == hipSuccess) { e = upload(&p->d_dqq, p->dqq); keep(p->d_dqq); }
   if (e == hipSuccess) { e = upload(&p->d_out_off, p->out_off); keep(p->d_out_off); }
-  if (e == hipSuccess) { e = upload(&p->d_item_wu_first, item_wu_first); keep(p->d_item_wu_first); }
-  if (e == hipSuccess) { e = upload(&p->d_item_wu_count, item_wu_count); keep(p->d_item_wu_count); }
-  if (e == hipSuccess) { e = upload(&p->d_rec_of_wu_grad, rec_of_wu_grad); keep(p->d_rec_of_wu_grad); }
-  if (e == hipSuccess) { e = upload(&p->d_rec_of_wu_ll, rec_of_wu_ll); keep(p->d_rec_of_wu_ll); }
+  auto upload_lists = [&](RecordLists& L, const std::vector<int64_t>& first,
+                          const std::vector<int32_t>& count, const std::vector<int64_t>& offs) {
+    if (e == hipSuccess) { e = upload(&L.first, first); keep(L.first); }
+    if (e == hipSuccess) { e = upload(&L.count, count); keep(L.count); }
+    if (e == hipSuccess) { e = upload(&L.offs, offs); keep(L.offs); }
+  };
+  upload_lists(p->lists_ll, ll_first, ll_count, ll_offs);
+  upload_lists(p->lists_grad, gr_first, gr_count, gr_offs);
   if (e == hipSuccess) {
     std::vector<double> rule(p->node_t, p->node_t + kSmearNodes);
     rule.insert(rule.end(), p->node_w, p->node_w + kSmearNodes);
@@ -309,32 +368,84 @@ nr_status nr_plan_create(const nr_batch_desc* d, nr_plan** out) {
     keep(p->d_rule);
   }
 
-  // one launch per non-empty bucket, heaviest buckets first, LPT order inside
-  std::vector<int> order;
-  for (int bk = 0; bk < kNumBuckets; ++bk)
-    if (!per_bucket[bk].empty()) order.push_back(bk);
-  std::sort(order.begin(), order.end(), [](int x, int y) { return x > y; });
-  for (int bk : order) {
-    if (e != hipSuccess) break;
-    auto& v = per_bucket[bk];
-    std::stable_sort(v.begin(), v.end(), [](const Wu& x, const Wu& y) { return x.cost > y.cost; });
-    std::vector<int32_t> it(v.size()), p0(v.size());
-    std::vector<int64_t> rg(v.size()), rl(v.size());
-    for (size_t k = 0; k < v.size(); ++k) {
-      it[k] = v[k].item;
-      p0[k] = v[k].p0;
-      rg[k] = rec_of_wu_grad[v[k].g];
-      rl[k] = rec_of_wu_ll[v[k].g];
+  // full-unit launches: one per non-empty bucket, deepest first, LPT order
+  auto make_full = [&](std::vector<std::vector<Wu>>& units, std::vector<Launch>& out_list) {
+    for (int bk = kNumBuckets - 1; bk >= 0; --bk) {
+      auto& v = units[bk];
+      if (v.empty() || e != hipSuccess) continue;
+      std::stable_sort(v.begin(), v.end(), [](const Wu& x, const Wu& y) { return x.cost > y.cost; });
+      std::vector<int32_t> it(v.size()), p0(v.size());
+      std::vector<int64_t> rc(v.size());
+      for (size_t k = 0; k < v.size(); ++k) {
+        it[k] = v[k].item;
+        p0[k] = v[k].p0;
+        rc[k] = v[k].rec;
+      }
+      Launch L;
+      L.bucket = bk;
+      L.n_wu = (int)v.size();
+      e = upload(&L.item, it);
+      keep(L.item);
+      if (e == hipSuccess) { e = upload(&L.p0, p0); keep(L.p0); }
+      if (e == hipSuccess) { e = upload(&L.rec, rc); keep(L.rec); }
+      out_list.push_back(L);
     }
-    Launch L;
-    L.bucket = bk;
-    L.n_wu = (int)v.size();
-    e = upload(&L.item, it);
-    keep(L.item);
-    if (e == hipSuccess) { e = upload(&L.p0, p0); keep(L.p0); }
-    if (e == hipSuccess) { e = upload(&L.rec_grad, rg); keep(L.rec_grad); }
-    if (e == hipSuccess) { e = upload(&L.rec_ll, rl); keep(L.rec_ll); }
-    p->launches.push_back(L);
+  };
+  make_full(fwd_units, p->launches_fwd);
+  make_full(grad_units, p->launches_grad);
+
+  // tail launches: per (depth, nodes) group, largest tails first, first fit
+  // into 64-lane units; then one launch per bucket over all its groups
+  {
+    std::vector<std::vector<int32_t>> b_item(kNumBuckets), b_litem(kNumBuckets), b_lpt(kNumBuckets);
+    std::vector<std::vector<int64_t>> b_lrec(kNumBuckets);
+    for (auto& kv : tails) {
+      const int bk = bucket_of(kv.first.first);
+      auto& v = kv.second;
+      std::stable_sort(v.begin(), v.end(),
+                       [](const Tail& x, const Tail& y) { return x.count > y.count; });
+      std::vector<int> fill;  // lanes used per unit of this group
+      std::vector<size_t> unit_base;
+      for (const Tail& t : v) {
+        size_t u = 0;
+        while (u < fill.size() && fill[u] + t.count > kWuPoints) ++u;
+        if (u == fill.size()) {
+          fill.push_back(0);
+          unit_base.push_back(b_item[bk].size());
+          b_item[bk].push_back(t.item);
+          b_litem[bk].insert(b_litem[bk].end(), kWuPoints, -1);
+          b_lpt[bk].insert(b_lpt[bk].end(), kWuPoints, 0);
+          b_lrec[bk].insert(b_lrec[bk].end(), kWuPoints, -1);
+        }
+        const size_t base = unit_base[u] * kWuPoints;
+        for (int l = 0; l < t.count; ++l) {
+          b_litem[bk][base + fill[u] + l] = t.item;
+          b_lpt[bk][base + fill[u] + l] = t.p0 + l;
+          b_lrec[bk][base + fill[u] + l] = t.rec0 + (int64_t)l * (3 + 4 * (kv.first.first + 2));
+        }
+        fill[u] += t.count;
+      }
+    }
+    for (int bk = kNumBuckets - 1; bk >= 0; --bk) {
+      if (b_item[bk].empty() || e != hipSuccess) continue;
+      // idle lanes repeat lane 0 of their unit (a valid point, result unused)
+      for (size_t u = 0; u < b_item[bk].size(); ++u)
+        for (int l = 0; l < kWuPoints; ++l)
+          if (b_litem[bk][u * kWuPoints + l] < 0) {
+            b_litem[bk][u * kWuPoints + l] = b_litem[bk][u * kWuPoints];
+            b_lpt[bk][u * kWuPoints + l] = b_lpt[bk][u * kWuPoints];
+          }
+      Launch L;
+      L.bucket = bk;
+      L.tail = true;
+      L.n_wu = (int)b_item[bk].size();
+      e = upload(&L.item, b_item[bk]);
+      keep(L.item);
+      if (e == hipSuccess) { e = upload(&L.lane_item, b_litem[bk]); keep(L.lane_item); }
+      if (e == hipSuccess) { e = upload(&L.lane_pt, b_lpt[bk]); keep(L.lane_pt); }
+      if (e == hipSuccess) { e = upload(&L.lane_rec, b_lrec[bk]); keep(L.lane_rec); }
+      p->launches_grad.push_back(L);
+    }
   }
   if (e != hipSuccess) {
     plan_free(p);
@@ -362,19 +473,9 @@ nr_status nr_plan_destroy(nr_plan* p) {
 
 nr_status nr_workspace_size(const nr_plan* p, int32_t op, size_t* bytes) {
   if (!p || !bytes) return NR_EINVAL;
-  switch (op) {
-    case NR_OP_REFLECTIVITY:
-      *bytes = 0;
-      return NR_OK;
-    case NR_OP_LOGLIK:
-      *bytes = sizeof(double) * (size_t)p->n_wu_total;
-      return NR_OK;
-    case NR_OP_LOGLIK_GRAD:
-      *bytes = sizeof(double) * (size_t)p->rec_grad_total;
-      return NR_OK;
-    default:
-      return NR_EINVAL;
-  }
+  if (op != NR_OP_REFLECTIVITY && op != NR_OP_LOGLIK && op != NR_OP_LOGLIK_GRAD) return NR_EINVAL;
+  *bytes = sizeof(double) * op_doubles(p, op);
+  return NR_OK;
 }
 
 nr_status nr_output_offsets(const nr_plan* p, int64_t* out_off) {
@@ -385,14 +486,14 @@ nr_status nr_output_offsets(const nr_plan* p, int64_t* out_off) {
 
 nr_status nr_reflectivity(const nr_plan* p, const nr_values* v, double* r_hat, void* ws,
                           size_t ws_bytes, void* stream) {
-  (void)ws;
-  (void)ws_bytes;
   nr_status st = check_call(p, v, false);
   if (st != NR_OK) return st;
   if (p->n_items == 0 || p->out_off.back() == 0) return NR_OK;
   if (!r_hat) return NR_EINVAL;
+  if (!ws || ws_bytes < sizeof(double) * op_doubles(p, NR_OP_REFLECTIVITY)) return NR_EWORKSPACE;
   KernelArgs a = base_args(p, v);
   a.out = r_hat;
+  a.consts = static_cast<double*>(ws);
   return run_launches(p, kOpReflectivity, a, (hipStream_t)stream);
 }
 
@@ -402,20 +503,21 @@ nr_status nr_loglik(const nr_plan* p, const nr_values* v, double* logL, void* ws
   if (st != NR_OK) return st;
   if (p->n_items == 0) return NR_OK;
   if (!logL) return NR_EINVAL;
-  const size_t need = sizeof(double) * (size_t)p->n_wu_total;
+  const size_t need = sizeof(double) * op_doubles(p, NR_OP_LOGLIK);
   if (need > 0 && (!ws || ws_bytes < need)) return NR_EWORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   KernelArgs a = base_args(p, v);
-  a.rec = static_cast<double*>(ws);
+  a.consts = static_cast<double*>(ws);
+  a.rec = static_cast<double*>(ws) + consts_doubles(p);
   st = run_launches(p, kOpLoglik, a, s);
   if (st != NR_OK) return st;
   ReduceArgs r;
   std::memset(&r, 0, sizeof(r));
   r.n_items = p->n_items;
-  r.item_wu_first = p->d_item_wu_first;
-  r.item_wu_count = p->d_item_wu_count;
-  r.rec_of_wu = p->d_rec_of_wu_ll;
-  r.rec = static_cast<double*>(ws);
+  r.item_wu_first = p->lists_ll.first;
+  r.item_wu_count = p->lists_ll.count;
+  r.rec_of_wu = p->lists_ll.offs;
+  r.rec = a.rec;
   r.logL = logL;
   hipError_t e = launch_reduce(kOpLoglik, r, s);
   return e == hipSuccess ? NR_OK : hip_fail(e, "reduce launch");
@@ -427,20 +529,21 @@ nr_status nr_loglik_grad(const nr_plan* p, const nr_values* v, double* logL, dou
   if (st != NR_OK) return st;
   if (p->n_items == 0) return NR_OK;
   if (!logL || !g_rows || !g_inst) return NR_EINVAL;
-  const size_t need = sizeof(double) * (size_t)p->rec_grad_total;
+  const size_t need = sizeof(double) * op_doubles(p, NR_OP_LOGLIK_GRAD);
   if (need > 0 && (!ws || ws_bytes < need)) return NR_EWORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   KernelArgs a = base_args(p, v);
-  a.rec = static_cast<double*>(ws);
+  a.consts = static_cast<double*>(ws);
+  a.rec = static_cast<double*>(ws) + consts_doubles(p);
   st = run_launches(p, kOpLoglikGrad, a, s);
   if (st != NR_OK) return st;
   ReduceArgs r;
   std::memset(&r, 0, sizeof(r));
   r.n_items = p->n_items;
-  r.item_wu_first = p->d_item_wu_first;
-  r.item_wu_count = p->d_item_wu_count;
-  r.rec_of_wu = p->d_rec_of_wu_grad;
-  r.rec = static_cast<double*>(ws);
+  r.item_wu_first = p->lists_grad.first;
+  r.item_wu_count = p->lists_grad.count;
+  r.rec_of_wu = p->lists_grad.offs;
+  r.rec = a.rec;
   r.row_off = p->d_row_off;
   r.layers = v->layers;
   r.logL = logL;

@@ -42,6 +42,10 @@ struct KernelArgs {
   const int32_t* wu_item;
   const int32_t* wu_p0;
   const int64_t* wu_rec;
+  // tail work units: per-lane item, point and record (64 per unit)
+  const int32_t* tail_item;
+  const int32_t* tail_pt;
+  const int64_t* tail_rec;
   // batch structure (plan-owned device copies)
   const int32_t* dataset_of_item;
   const int64_t* q_off;
@@ -57,12 +61,14 @@ struct KernelArgs {
   const double* bkg;
   int32_t* item_status;
   // outputs
-  double* out;  // nr_reflectivity
-  double* rec;  // workspace records
+  double* out;     // nr_reflectivity
+  double* rec;     // workspace records
+  const double* consts;  // workspace: per-item layer records (6 doubles per row)
   // plan-owned constants (device): quadrature node offsets in units of
   // sigma_Q and normalised weights (kSmearNodes each), then the tables
   // (sin, cos)(k pi/32) for k = 0..63 interleaved and 2^(j/64), j = 0..63
   const double* rule;
+  int zero_mask;  // always 0 (see the layer-record indexing in the kernels)
 };
 
 struct ReduceArgs {
@@ -78,8 +84,10 @@ struct ReduceArgs {
   double* g_inst;
 };
 
+hipError_t launch_item_consts(const int64_t* row_off, const double* layers, double* rec,
+                              int n_items, hipStream_t st);
 hipError_t launch_forward(int op, const KernelArgs& a, int n_wu, hipStream_t st);
-hipError_t launch_grad(int bucket, const KernelArgs& a, int n_wu, hipStream_t st);
+hipError_t launch_grad(int bucket, bool tail, const KernelArgs& a, int n_wu, hipStream_t st);
 hipError_t launch_reduce(int op, const ReduceArgs& a, hipStream_t st);
 
 }  // namespace nr

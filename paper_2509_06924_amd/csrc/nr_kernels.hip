@@ -4,8 +4,8 @@
 //
 // Work decomposition: one work unit (WU) = one item x up to 64 consecutive data
 // points of its dataset, one wave (64 lanes) per WU, lane = data point.  The
-// item is wave-uniform, so its layer constants are staged once per wave in LDS
-// and read as broadcasts.  A lane walks all quadrature nodes of its point; for
+// item is wave-uniform, so its per-layer constants (precomputed per item by a
+// small prologue kernel) are read with scalar loads into scalar registers.  A lane walks all quadrature nodes of its point; for
 // each node it runs the layer product bottom-up (substrate -> surface), then
 // the adjoint top down, and accumulates w_k dR(q_k)/d(theta) in registers;
 // the point's likelihood seed multiplies the accumulators once at the end.
@@ -18,8 +18,8 @@
 //
 // Two gradient variants (one source, selected by template):
 //   store     - the forward sweep keeps each level's state (P, Qv) and phase
-//               e_j in LDS and each medium's kz_j, 1/|kz_j|^2 in registers;
-//               the adjoint recomputes only the interface coefficients.
+//               e_j in LDS and each medium's kz_j, 1/|kz_j|^2 and interface
+//               coefficients in registers; the adjoint recomputes nothing.
 //   recompute - for deep stacks: the state tape stays in registers and the
 //               adjoint recomputes every layer's wavevector and phase.
 #include <hip/hip_runtime.h>
@@ -33,42 +33,80 @@
 namespace nr {
 
 // ---------------------------------------------------------------------------
-// Per-item constants in LDS, indexed by medium m = 0..N+1 / interface j = 0..N
-//   A[m]  = 4 pi (rho_re,m - rho_re,0)        (A[0] = 0)
-//   B[m]  = 4 pi |rho_im,m|                   (B[0] = 0: fronting is lossless)
-//   D[m]  = 2 d_m                             (layers 1..N)
-//   C[j]  = -2 sigma_{j+1}^2                  (Nevot-Croce exponent factor)
-//   Nr/Ni[j] = w_j - w_{j+1} = (A[j+1]-A[j]) + i (B[j+1]-B[j]),
-//           the Q-independent numerator of r_j = (w_j - w_{j+1})/(kz_j + kz_{j+1})^2
-// plus the quadrature rule and the exp/sincos tables.
+// Per-item layer records, written by k_item_consts into the workspace (six
+// doubles per medium m = 0..N+1, indexed like the item's rows) and read by the
+// main kernels with scalar loads, since every lane of a wave uses the same
+// item:
+//   A  = 4 pi (rho_re,m - rho_re,0)        (0 for the fronting medium)
+//   B  = 4 pi |rho_im,m|                   (0 for the fronting: lossless)
+//   Nr + i Ni = w_m - w_{m+1} = (A_{m+1} - A_m) + i (B_{m+1} - B_m), the
+//        Q-independent numerator of r_m = (w_m - w_{m+1}) / (kz_m + kz_{m+1})^2
+//   C  = -2 sigma_{m+1}^2                  (Nevot-Croce exponent factor)
+//   D  = 2 d_m                             (layers 1..N)
+// Interface fields of the backing record are 0.
 // ---------------------------------------------------------------------------
-struct ItemConsts {
-  double A[kMaxLayers + 2], B[kMaxLayers + 2], D[kMaxLayers + 2], C[kMaxLayers + 2],
-      Nr[kMaxLayers + 2], Ni[kMaxLayers + 2];
+constexpr int kRec = 6;
+
+struct Layers {
+  const double* rec;  // the item's records
+  int z;              // an opaque zero (see opaque_zero)
+  __device__ __forceinline__ double at(int m, int f) const { return rec[(m + z) * kRec + f]; }
+  __device__ __forceinline__ double A(int m) const { return at(m, 0); }
+  __device__ __forceinline__ double B(int m) const { return at(m, 1); }
+  __device__ __forceinline__ double Nr(int m) const { return at(m, 2); }
+  __device__ __forceinline__ double Ni(int m) const { return at(m, 3); }
+  __device__ __forceinline__ double C(int m) const { return at(m, 4); }
+  __device__ __forceinline__ double D(int m) const { return at(m, 5); }
+};
+
+// Layer records are indexed with (m + z) where z = k & KernelArgs::zero_mask
+// (the mask is 0): z is 0 at run time but varies with the node counter k as
+// far as the compiler can tell, so the records are re-read (with scalar
+// loads) inside the node loop instead of being hoisted out of it, which would
+// need far more scalar registers than exist.
+
+// One block of 64 per item, one lane per medium.
+__global__ __launch_bounds__(64) void k_item_consts(const int64_t* row_off, const double* layers,
+                                                    double* rec, int n_items) {
+  const int b = blockIdx.x;
+  const int m = threadIdx.x;
+  if (b >= n_items) return;
+  const int64_t r0 = row_off[b];
+  const int NR = (int)(row_off[b + 1] - r0);
+  if (m >= NR) return;
+  const double* rows = layers + 4 * r0;
+  const double rho0 = rows[1];
+  auto Af = [&](int j) { return (j == 0) ? 0.0 : kFourPi * (rows[4 * j + 1] - rho0); };
+  auto Bf = [&](int j) { return (j == 0) ? 0.0 : kFourPi * fabs(rows[4 * j + 2]); };
+  double* out = rec + (r0 + m) * kRec;
+  const double A = Af(m), B = Bf(m);
+  out[0] = A;
+  out[1] = B;
+  if (m + 1 < NR) {
+    const double sg = rows[4 * (m + 1) + 3];
+    out[2] = Af(m + 1) - A;
+    out[3] = Bf(m + 1) - B;
+    out[4] = -2.0 * (sg * sg);
+  } else {
+    out[2] = 0.0;
+    out[3] = 0.0;
+    out[4] = 0.0;
+  }
+  out[5] = 2.0 * rows[4 * m];
+}
+
+// The quadrature rule and the exp/sincos tables, staged per block in LDS.
+struct Shared {
   double t[kSmearNodes], w[kSmearNodes];
   MathTables tab;
 };
 
-// Reads of the staged constants are volatile so that the compiler re-reads
-// them from LDS at every use instead of keeping every layer's constants in
-// registers across the node loop.
+// Reads of staged LDS values that every lane shares are volatile so that the
+// compiler re-reads them at each use instead of holding them in registers.
 typedef __attribute__((address_space(3))) const volatile double lds_cv_double;
 __device__ __forceinline__ double ld(const double& x) { return *(lds_cv_double*)(&x); }
 
-__device__ __forceinline__ void stage_item(ItemConsts& s, const double* rows, int N, int lane,
-                                           const double* rule) {
-  // rows: (N+2) x 4, [d, rho_re, rho_im, sigma]
-  if (lane <= N + 1) {
-    const double rho0 = rows[1];
-    const double* r = rows + 4 * lane;
-    s.A[lane] = (lane == 0) ? 0.0 : kFourPi * (r[1] - rho0);
-    s.B[lane] = (lane == 0) ? 0.0 : kFourPi * fabs(r[2]);
-    s.D[lane] = 2.0 * r[0];
-    if (lane <= N) {
-      const double sg = rows[4 * (lane + 1) + 3];
-      s.C[lane] = -2.0 * (sg * sg);
-    }
-  }
+__device__ __forceinline__ void stage_shared(Shared& s, int lane, const double* rule) {
   if (lane < kSmearNodes) {
     s.t[lane] = rule[lane];
     s.w[lane] = rule[kSmearNodes + lane];
@@ -78,11 +116,6 @@ __device__ __forceinline__ void stage_item(ItemConsts& s, const double* rows, in
   s.tab.sc[lane][0] = tb[2 * lane];
   s.tab.sc[lane][1] = tb[2 * lane + 1];
   s.tab.e2[lane] = tb[128 + lane];
-  __syncthreads();
-  if (lane <= N) {
-    s.Nr[lane] = s.A[lane + 1] - s.A[lane];
-    s.Ni[lane] = s.B[lane + 1] - s.B[lane];
-  }
   __syncthreads();
 }
 
@@ -113,29 +146,29 @@ __device__ __forceinline__ cd layer_phase(const MathTables& T, cd kz, double D) 
   return cexp_tab(T, mk(D * kz.im, -D * kz.re));
 }
 
-__device__ __forceinline__ Root medium_root(const ItemConsts& s, double kz0sq, int m) {
-  return kz_root(kz_real_part(kz0sq, ld(s.A[m])), -ld(s.B[m]));
+__device__ __forceinline__ Root medium_root(const Layers& L, double kz0sq, int m) {
+  return kz_root(kz_real_part(kz0sq, L.A(m)), -L.B(m));
 }
 
 // ---------------------------------------------------------------------------
 // Forward-only reflectivity of one node (no state kept; runtime layer loop).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double node_reflectivity(const ItemConsts& s, int N, double q) {
+__device__ __forceinline__ double node_reflectivity(const MathTables& T, const Layers& L, int N,
+                                                    double q) {
   const double kz0sq = kz0_squared(q);
-  cd kzn = medium_root(s, kz0sq, N + 1).kz;
+  cd kzn = medium_root(L, kz0sq, N + 1).kz;
   cd P = mk(1.0, 0.0), Qv = mk(0.0, 0.0);
   for (int jj = N; jj >= 1; --jj) {
-    const cd kzc = medium_root(s, kz0sq, jj).kz;
-    const Iface it = interface_coeffs(s.tab, kzc, kzn, ld(s.Nr[jj]), ld(s.Ni[jj]), ld(s.C[jj]));
+    const cd kzc = medium_root(L, kz0sq, jj).kz;
+    const Iface it = interface_coeffs(T, kzc, kzn, L.Nr(jj), L.Ni(jj), L.C(jj));
     const cd Pn = P + it.rp * Qv;
     const cd t = it.rp * P + Qv;
-    Qv = layer_phase(s.tab, kzc, ld(s.D[jj])) * t;
+    Qv = layer_phase(T, kzc, L.D(jj)) * t;
     P = Pn;
     kzn = kzc;
   }
   {
-    const Iface it =
-        interface_coeffs(s.tab, mk(0.5 * q, 0.0), kzn, ld(s.Nr[0]), ld(s.Ni[0]), ld(s.C[0]));
+    const Iface it = interface_coeffs(T, mk(0.5 * q, 0.0), kzn, L.Nr(0), L.Ni(0), L.C(0));
     const cd Pn = P + it.rp * Qv;
     Qv = it.rp * P + Qv;
     P = Pn;
@@ -168,6 +201,28 @@ __device__ __forceinline__ WuInfo wu_setup(const KernelArgs& a, int w, int lane)
   return u;
 }
 
+// Tail work units pack the last partial group of points of several items of
+// equal depth into one wave: lane l evaluates point tail_pt[l] of item
+// tail_item[l] and writes its own record at tail_rec[l] (idle lanes have
+// tail_rec = -1 and repeat lane 0's point).  The depth is wave-uniform and
+// taken from wu_item[w].
+__device__ __forceinline__ WuInfo tail_setup(const KernelArgs& a, int w, int lane) {
+  WuInfo u;
+  const int first = a.wu_item[w];
+  u.N = (int)(a.row_off[first + 1] - a.row_off[first]) - 2;
+  const int64_t slot = (int64_t)w * 64 + lane;
+  u.active = a.tail_rec[slot] >= 0;
+  u.item = a.tail_item[slot];
+  u.i = a.tail_pt[slot];
+  u.ds = a.dataset_of_item[u.item];
+  u.qoff = a.q_off[u.ds];
+  u.nq = (int)(a.q_off[u.ds + 1] - u.qoff);
+  u.roff = a.row_off[u.item];
+  u.Q = a.q[u.qoff + u.i];
+  u.dqq = a.dq_over_q[u.ds];
+  return u;
+}
+
 __device__ __forceinline__ void flag(int32_t* status, int item, uint32_t bits) {
   if (status != nullptr && bits != 0u)
     atomicOr(reinterpret_cast<unsigned int*>(status + item), bits);
@@ -177,11 +232,12 @@ __device__ __forceinline__ void flag(int32_t* status, int item, uint32_t bits) {
 // R_hat per point (nr_reflectivity).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_reflectivity(KernelArgs a) {
-  __shared__ ItemConsts s;
+  __shared__ Shared s;
   const int lane = threadIdx.x;
   const int w = blockIdx.x;
   const WuInfo u = wu_setup(a, w, lane);
-  stage_item(s, a.layers + 4 * u.roff, u.N, lane, a.rule);
+  stage_shared(s, lane, a.rule);
+  const double* lrec = a.consts + u.roff * kRec;
   const int K = (u.dqq > 0.0) ? kSmearNodes : 1;
   double Rsm = 0.0;
   bool badq = !(u.Q > 0.0);
@@ -189,7 +245,8 @@ __global__ __launch_bounds__(64) void k_reflectivity(KernelArgs a) {
     const double q = (K == 1) ? u.Q : smear_node(u.Q, u.dqq, ld(s.t[k]));
     badq |= !(q > 0.0);
     const double wk = (K == 1) ? 1.0 : ld(s.w[k]);
-    Rsm += wk * node_reflectivity(s, u.N, q);
+    const Layers L{lrec, k & a.zero_mask};
+    Rsm += wk * node_reflectivity(s.tab, L, u.N, q);
   }
   if (u.active) {
     double Rhat = a.scale[u.item] * Rsm + a.bkg[u.item];
@@ -220,11 +277,12 @@ __device__ __forceinline__ double point_loglik(double Rhat, double Robs, double 
 // logL partial per WU (nr_loglik): record = 1 double.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_loglik(KernelArgs a) {
-  __shared__ ItemConsts s;
+  __shared__ Shared s;
   const int lane = threadIdx.x;
   const int w = blockIdx.x;
   const WuInfo u = wu_setup(a, w, lane);
-  stage_item(s, a.layers + 4 * u.roff, u.N, lane, a.rule);
+  stage_shared(s, lane, a.rule);
+  const double* lrec = a.consts + u.roff * kRec;
   const int K = (u.dqq > 0.0) ? kSmearNodes : 1;
   double Rsm = 0.0;
   bool badq = !(u.Q > 0.0);
@@ -232,7 +290,8 @@ __global__ __launch_bounds__(64) void k_loglik(KernelArgs a) {
     const double q = (K == 1) ? u.Q : smear_node(u.Q, u.dqq, ld(s.t[k]));
     badq |= !(q > 0.0);
     const double wk = (K == 1) ? 1.0 : ld(s.w[k]);
-    Rsm += wk * node_reflectivity(s, u.N, q);
+    const Layers L{lrec, k & a.zero_mask};
+    Rsm += wk * node_reflectivity(s.tab, L, u.N, q);
   }
   double ll = 0.0;
   uint32_t bits = 0;
@@ -320,9 +379,9 @@ __device__ __forceinline__ cd from_d2(double2 v) { return mk(v.x, v.y); }
 // then the adjoint.  Returns R(q) and adds w_k dR/d(.) to the accumulators.
 // ---------------------------------------------------------------------------
 template <int LMAX>
-__device__ __forceinline__ double node_grad_store(const ItemConsts& s, GradTape<LMAX>& tp,
-                                                  Accum<LMAX>& acc, int N, int lane, double q,
-                                                  double wk) {
+__device__ __forceinline__ double node_grad_store(const MathTables& T, const Layers& L,
+                                                  GradTape<LMAX>& tp, Accum<LMAX>& acc, int N,
+                                                  int lane, double q, double wk) {
   const double kz0sq = kz0_squared(q);
   cd kz[LMAX + 2];
   double ia[LMAX + 2];
@@ -331,7 +390,7 @@ __device__ __forceinline__ double node_grad_store(const ItemConsts& s, GradTape<
 #pragma unroll
   for (int jj = LMAX + 1; jj >= 0; --jj) {
     if (jj == N + 1) {
-      const Root rt = medium_root(s, kz0sq, jj);
+      const Root rt = medium_root(L, kz0sq, jj);
       kz[jj] = rt.kz;
       ia[jj] = rt.inv_abs2;
     } else if (jj <= N) {
@@ -339,19 +398,19 @@ __device__ __forceinline__ double node_grad_store(const ItemConsts& s, GradTape<
         kz[0] = mk(0.5 * q, 0.0);
         ia[0] = 0.0;
       } else {
-        const Root rt = medium_root(s, kz0sq, jj);
+        const Root rt = medium_root(L, kz0sq, jj);
         kz[jj] = rt.kz;
         ia[jj] = rt.inv_abs2;
       }
       const Iface it =
-          interface_coeffs(s.tab, kz[jj], kz[jj + 1], ld(s.Nr[jj]), ld(s.Ni[jj]), ld(s.C[jj]));
+          interface_coeffs(T, kz[jj], kz[jj + 1], L.Nr(jj), L.Ni(jj), L.C(jj));
       ifc[jj] = it;
       tp.P[jj][lane] = to_d2(P);
       tp.Qv[jj][lane] = to_d2(Qv);
       const cd Pn = P + it.rp * Qv;
       const cd t = it.rp * P + Qv;
       if (jj >= 1) {
-        const cd e = layer_phase(s.tab, kz[jj], ld(s.D[jj]));
+        const cd e = layer_phase(T, kz[jj], L.D(jj));
         tp.E[jj][lane] = to_d2(e);
         Qv = e * t;
       } else {
@@ -359,7 +418,6 @@ __device__ __forceinline__ double node_grad_store(const ItemConsts& s, GradTape<
       }
       P = Pn;
     }
-    __builtin_amdgcn_sched_barrier(0);
   }
   const cd iP = crecip(P);
   const cd r = Qv * iP;
@@ -370,14 +428,14 @@ __device__ __forceinline__ double node_grad_store(const ItemConsts& s, GradTape<
 #pragma unroll
   for (int jj = 0; jj <= LMAX; ++jj) {
     if (jj <= N) {
-      const double C = ld(s.C[jj]);
+      const double C = L.C(jj);
       const Iface& it = ifc[jj];
       const cd Ps = from_d2(tp.P[jj][lane]);
       const cd Qs = from_d2(tp.Qv[jj][lane]);
       const bool ph = jj >= 1;
       const cd e = ph ? from_d2(tp.E[jj][lane]) : mk(1.0, 0.0);
       const AdjStep st =
-          adjoint_step(Ps, Qs, Pb, Qb, kz[jj], kz[jj + 1], it, C, ph, e, ph ? ld(s.D[jj]) : 0.0);
+          adjoint_step(Ps, Qs, Pb, Qb, kz[jj], kz[jj + 1], it, C, ph, e, ph ? L.D(jj) : 0.0);
       kzbc += st.kzb_c;
       acc.Hs[jj + 1] += st.ss;
       if (ph) {
@@ -389,7 +447,6 @@ __device__ __forceinline__ double node_grad_store(const ItemConsts& s, GradTape<
       Qb = st.Qb;
       kzbc = st.kzb_n;
     }
-    __builtin_amdgcn_sched_barrier(0);
   }
   return cabs2(r);
 }
@@ -399,27 +456,28 @@ __device__ __forceinline__ double node_grad_store(const ItemConsts& s, GradTape<
 // recomputes each medium's wavevector and each layer's phase.
 // ---------------------------------------------------------------------------
 template <int LMAX>
-__device__ __forceinline__ double node_grad_recompute(const ItemConsts& s, Accum<LMAX>& acc, int N,
-                                                      double q, double wk) {
+__device__ __forceinline__ double node_grad_recompute(const MathTables& T, const Layers& L,
+                                                      Accum<LMAX>& acc, int N, double q,
+                                                      double wk) {
   const double kz0sq = kz0_squared(q);
   const cd kz0 = mk(0.5 * q, 0.0);
   cd tapeP[LMAX + 1], tapeQ[LMAX + 1];
-  cd kzn = medium_root(s, kz0sq, N + 1).kz;
+  cd kzn = medium_root(L, kz0sq, N + 1).kz;
   cd P = mk(1.0, 0.0), Qv = mk(0.0, 0.0);
 #pragma unroll
   for (int jj = LMAX; jj >= 0; --jj) {
     if (jj <= N) {
-      const cd kzc = (jj == 0) ? kz0 : medium_root(s, kz0sq, jj).kz;
+      const cd kzc = (jj == 0) ? kz0 : medium_root(L, kz0sq, jj).kz;
       tapeP[jj] = P;
       tapeQ[jj] = Qv;
-      const Iface it = interface_coeffs(s.tab, kzc, kzn, ld(s.Nr[jj]), ld(s.Ni[jj]), ld(s.C[jj]));
+      const Iface it = interface_coeffs(T, kzc, kzn, L.Nr(jj), L.Ni(jj), L.C(jj));
       const cd Pn = P + it.rp * Qv;
       const cd t = it.rp * P + Qv;
-      Qv = (jj >= 1) ? layer_phase(s.tab, kzc, ld(s.D[jj])) * t : t;
+      Qv = (jj >= 1) ? layer_phase(T, kzc, L.D(jj)) * t : t;
       P = Pn;
       kzn = kzc;
     }
-    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_sched_barrier(0x0100);  // only LDS reads may move across
   }
   const cd iP = crecip(P);
   const cd r = Qv * iP;
@@ -432,12 +490,12 @@ __device__ __forceinline__ double node_grad_recompute(const ItemConsts& s, Accum
 #pragma unroll
   for (int jj = 0; jj <= LMAX; ++jj) {
     if (jj <= N) {
-      const Root rn = medium_root(s, kz0sq, jj + 1);
-      const double C = ld(s.C[jj]);
-      const Iface it = interface_coeffs(s.tab, kzc, rn.kz, ld(s.Nr[jj]), ld(s.Ni[jj]), C);
+      const Root rn = medium_root(L, kz0sq, jj + 1);
+      const double C = L.C(jj);
+      const Iface it = interface_coeffs(T, kzc, rn.kz, L.Nr(jj), L.Ni(jj), C);
       const bool ph = jj >= 1;
-      const double D = ph ? ld(s.D[jj]) : 0.0;
-      const cd e = ph ? layer_phase(s.tab, kzc, D) : mk(1.0, 0.0);
+      const double D = ph ? L.D(jj) : 0.0;
+      const cd e = ph ? layer_phase(T, kzc, D) : mk(1.0, 0.0);
       const AdjStep st = adjoint_step(tapeP[jj], tapeQ[jj], Pb, Qb, kzc, rn.kz, it, C, ph, e, D);
       kzbc += st.kzb_c;
       acc.Hs[jj + 1] += st.ss;
@@ -452,7 +510,7 @@ __device__ __forceinline__ double node_grad_recompute(const ItemConsts& s, Accum
       iac = rn.inv_abs2;
       kzbc = st.kzb_n;
     }
-    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_sched_barrier(0x0100);  // only LDS reads may move across
   }
   return cabs2(r);
 }
@@ -466,15 +524,16 @@ __device__ __forceinline__ double node_grad_recompute(const ItemConsts& s, Accum
 //   [3 + 2NR + m]  sum dl/dd_m
 //   [3 + 3NR + m]  sum Re(conj(ubar) kz_{m-1} kz_m)   (sigma_m factor applied later)
 // ---------------------------------------------------------------------------
-template <int LMAX, bool STORE>
+template <int LMAX, bool STORE, bool TAIL>
 __global__ __launch_bounds__(64) void k_loglik_grad(KernelArgs a) {
-  __shared__ ItemConsts s;
+  __shared__ Shared s;
   using Tape = typename std::conditional<STORE, GradTape<LMAX>, char>::type;
   __shared__ Tape tape;
   const int lane = threadIdx.x;
   const int w = blockIdx.x;
-  const WuInfo u = wu_setup(a, w, lane);
-  stage_item(s, a.layers + 4 * u.roff, u.N, lane, a.rule);
+  const WuInfo u = TAIL ? tail_setup(a, w, lane) : wu_setup(a, w, lane);
+  stage_shared(s, lane, a.rule);
+  const double* lrec = a.consts + u.roff * kRec;
   const int N = u.N;
   const int K = (u.dqq > 0.0) ? kSmearNodes : 1;
 
@@ -492,11 +551,12 @@ __global__ __launch_bounds__(64) void k_loglik_grad(KernelArgs a) {
     const double q = (K == 1) ? u.Q : smear_node(u.Q, u.dqq, ld(s.t[k]));
     badq |= !(q > 0.0);
     const double wk = (K == 1) ? 1.0 : ld(s.w[k]);
+    const Layers L{lrec, k & a.zero_mask};
     double R;
     if constexpr (STORE)
-      R = node_grad_store<LMAX>(s, tape, acc, N, lane, q, wk);
+      R = node_grad_store<LMAX>(s.tab, L, tape, acc, N, lane, q, wk);
     else
-      R = node_grad_recompute<LMAX>(s, acc, N, q, wk);
+      R = node_grad_recompute<LMAX>(s.tab, L, acc, N, q, wk);
     Rsm += wk * R;
   }
 
@@ -515,9 +575,28 @@ __global__ __launch_bounds__(64) void k_loglik_grad(KernelArgs a) {
   }
   flag(a.item_status, u.item, bits);
 
+  const int NR = N + 2;
+  if constexpr (TAIL) {
+    // one record per lane
+    if (u.active) {
+      double* rec = a.rec + a.tail_rec[(int64_t)w * 64 + lane];
+      rec[0] = ll;
+      rec[1] = gsc;
+      rec[2] = gbk;
+#pragma unroll
+      for (int m = 0; m < LMAX + 2; ++m) {
+        if (m < NR) {
+          rec[3 + m] = fac * acc.Hw[m].re;
+          rec[3 + NR + m] = fac * acc.Hw[m].im;
+          rec[3 + 2 * NR + m] = fac * acc.Hd[m];
+          rec[3 + 3 * NR + m] = fac * acc.Hs[m];
+        }
+      }
+    }
+    return;
+  }
   // ---- wave reduction and record ----
   double* rec = a.rec + a.wu_rec[w];
-  const int NR = N + 2;
   ll = wave_sum(ll);
   gsc = wave_sum(gsc);
   gbk = wave_sum(gbk);
@@ -606,6 +685,13 @@ __global__ __launch_bounds__(64) void k_reduce_grad(ReduceArgs a) {
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+hipError_t launch_item_consts(const int64_t* row_off, const double* layers, double* rec,
+                              int n_items, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_item_consts, dim3(n_items), dim3(64), 0, st, row_off, layers, rec, n_items);
+  return hipGetLastError();
+}
+
 hipError_t launch_forward(int op, const KernelArgs& a, int n_wu, hipStream_t st) {
   if (n_wu <= 0) return hipSuccess;
   if (op == kOpReflectivity)
@@ -615,13 +701,17 @@ hipError_t launch_forward(int op, const KernelArgs& a, int n_wu, hipStream_t st)
   return hipGetLastError();
 }
 
-hipError_t launch_grad(int bucket, const KernelArgs& a, int n_wu, hipStream_t st) {
+hipError_t launch_grad(int bucket, bool tail, const KernelArgs& a, int n_wu, hipStream_t st) {
   if (n_wu <= 0) return hipSuccess;
   switch (kBucketLmax[bucket]) {
-#define NR_CASE(LM)                                                                         \
-  case LM:                                                                                  \
-    hipLaunchKernelGGL((k_loglik_grad<LM, (LM <= kStoreMaxLayers)>), dim3(n_wu), dim3(64), 0, \
-                       st, a);                                                              \
+#define NR_CASE(LM)                                                                           \
+  case LM:                                                                                    \
+    if (tail)                                                                                 \
+      hipLaunchKernelGGL((k_loglik_grad<LM, (LM <= kStoreMaxLayers), true>), dim3(n_wu),      \
+                         dim3(64), 0, st, a);                                                 \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_loglik_grad<LM, (LM <= kStoreMaxLayers), false>), dim3(n_wu),     \
+                         dim3(64), 0, st, a);                                                 \
     return hipGetLastError();
     NR_BUCKETS(NR_CASE)
 #undef NR_CASE
