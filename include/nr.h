@@ -155,6 +155,93 @@ nr_status nr_loglik_grad(const nr_plan* plan, const nr_values* v, double* logL,
                          double* g_rows, double* g_inst, void* workspace,
                          size_t workspace_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Integrators and co-fit ties around the gradient.
+ * ------------------------------------------------------------------------- */
+
+/* Positions, momenta and gradient of an HMC state (all DEVICE pointers,
+ * packed like the rows; instrument pairs [scale, bkg] per item). */
+typedef struct nr_hmc_state {
+  double* layers;              /* [row_off[n_items] * 4] positions */
+  double* scale;               /* [n_items] */
+  double* bkg;                 /* [n_items] */
+  double* mom_rows;            /* [row_off[n_items] * 4] momenta */
+  double* mom_inst;            /* [2 * n_items] momenta of (scale, bkg) */
+  const double* inv_mass_rows; /* optional [row_off[n_items] * 4]; NULL = 1 */
+  const double* inv_mass_inst; /* optional [2 * n_items]; NULL = 1 */
+  double* logL;                /* [n_items] logL at the positions */
+  double* g_rows;              /* [row_off[n_items] * 4] gradient of logL */
+  double* g_inst;              /* [2 * n_items] */
+} nr_hmc_state;
+
+/* n_steps leapfrog steps of Hamiltonian dynamics for every item (Sec. 2.3,
+ * leapfrog equations) with potential U = -logL (flat priors) and kinetic
+ * energy r^T M^-1 r / 2, M diagonal:
+ *   r <- r + (dt/2) g;  theta <- theta + dt M^-1 r;  (logL, g) at theta;
+ *   r <- r + (dt/2) g.
+ * On entry st->logL, g_rows, g_inst must hold the values at the positions
+ * (one nr_loglik_grad call before the first step).  Entries the model does
+ * not read are never moved; an inverse mass of 0 freezes an entry.  `data`
+ * supplies q, r_obs, r_err and the optional status array (its layers, scale
+ * and bkg are ignored).  Uses the NR_OP_LOGLIK_GRAD workspace. */
+nr_status nr_leapfrog(const nr_plan* plan, const nr_values* data, const nr_hmc_state* st,
+                      double dt, int32_t n_steps, void* workspace, size_t workspace_bytes,
+                      void* stream);
+
+/* A captured sequence of launches (HIP graph). */
+typedef struct nr_graph nr_graph;
+
+/* Captures nr_leapfrog(plan, data, st, dt, n_steps, ...) into a HIP graph on
+ * an internal stream.  Every pointer (including the contents of *data and
+ * *st) is baked in and must stay valid until nr_graph_destroy.  Allocates
+ * host and device resources for the graph; not graph-capturable itself. */
+nr_status nr_leapfrog_graph_create(const nr_plan* plan, const nr_values* data,
+                                   const nr_hmc_state* st, double dt, int32_t n_steps,
+                                   void* workspace, size_t workspace_bytes, nr_graph** graph_out);
+
+/* Replays a captured graph on `stream`. */
+nr_status nr_graph_launch(nr_graph* graph, void* stream);
+
+/* Releases a graph.  NULL is accepted. */
+nr_status nr_graph_destroy(nr_graph* graph);
+
+/* Reparameterised Monte-Carlo gradient of the evidence lower bound for a
+ * mean-field Gaussian q (Sec. 2.4, Monte-Carlo estimate of the loss and of its
+ * gradient; reparameterisation theta = mu + s(omega) eps with
+ * s = softplus).  The plan's items are the S samples; each must have the
+ * same number of rows `rows`.  P = rows * 4 + 2 entries per sample: the rows
+ * of one stack, then scale, bkg.  On variational entries (mask != 0)
+ * theta_i = mu + s eps_i, elsewhere theta_i = mu.  Outputs (device):
+ *   logL[i], g_rows, g_inst per sample (as nr_loglik_grad);
+ *   grad_mu[p] = mean_i g_ip, grad_omega[p] = mean_i g_ip eps_ip s'(omega_p)
+ *   + s'(omega_p)/s(omega_p) (0 outside the mask), the gradient of
+ *   ELBO = mean_i logL_i + sum_p ln s(omega_p) (+ const), whose estimate is
+ *   written to elbo[0].  Flat priors.  Uses the NR_OP_LOGLIK_GRAD workspace. */
+typedef struct nr_vi_args {
+  const double* mu;     /* [P] */
+  const double* omega;  /* [P] */
+  const uint8_t* mask;  /* [P] */
+  const double* eps;    /* [S * P] standard normal draws (caller's RNG) */
+  double* layers;       /* [S * rows * 4] sample positions (written) */
+  double* scale;        /* [S] */
+  double* bkg;          /* [S] */
+  double* logL;         /* [S] */
+  double* g_rows;       /* [S * rows * 4] */
+  double* g_inst;       /* [2 * S] */
+  double* grad_mu;      /* [P] */
+  double* grad_omega;   /* [P] */
+  double* elbo;         /* [1] */
+} nr_vi_args;
+nr_status nr_vi_elbo_grad(const nr_plan* plan, const nr_values* data, const nr_vi_args* vi,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
+/* Deterministic gather-sum for parameters shared between co-fitted items
+ * (Sec. 4.2: instrument and substrate parameters shared across devices):
+ *   out[k] = sum of in[src[t]] for t = first[k] .. first[k+1]-1, in order.
+ * All arrays on the device; first has n_out + 1 entries. */
+nr_status nr_tie_sum(int64_t n_out, const int64_t* first, const int64_t* src, const double* in,
+                     double* out, void* stream);
+
 /* Optional timing hooks for profiling: while set, every evaluation call
  * records `start` (a hipEvent_t owned by the caller) on its stream just
  * before its first layer-product kernel and `stop` just after its last one,

@@ -21,7 +21,7 @@ from ._native import (NR_F32, NR_F64, NR_ITEM_BAD_ERR, NR_ITEM_BAD_Q,  # noqa: F
                       NR_OP_LOGLIK_GRAD, NR_OP_REFLECTIVITY, NativeError)
 
 __all__ = ["Plan", "Problem", "NRLogLik", "nr_reflectivity", "nr_loglik", "nr_loglik_grad",
-           "pack_theta", "NativeError"]
+           "pack_theta", "NativeError", "HmcState", "LeapfrogGraph", "tie_sum", "tie_map_to_csr"]
 
 
 def _ptr(a):
@@ -179,6 +179,127 @@ class Problem:
         nr_loglik_grad(self.plan, self.values(layers, scale, bkg), logL, g_rows, g_inst,
                        self.workspace(NR_OP_LOGLIK_GRAD), stream)
         return logL, g_rows, g_inst
+
+
+class HmcState:
+    """Device tensors of an HMC state: positions (copies of the problem's
+    parameters), momenta, optional inverse masses, and logL/gradient at the
+    positions."""
+
+    def __init__(self, problem, mom_rows, mom_inst, inv_mass_rows=None, inv_mass_inst=None):
+        import torch
+        f = dict(dtype=torch.float64, device=problem.device)
+        self.layers = problem.layers.clone()
+        self.scale = problem.scale.clone()
+        self.bkg = problem.bkg.clone()
+        self.mom_rows = torch.as_tensor(mom_rows, **f).reshape(-1, 4).contiguous().clone()
+        self.mom_inst = torch.as_tensor(mom_inst, **f).reshape(-1, 2).contiguous().clone()
+        self.inv_mass_rows = None if inv_mass_rows is None else \
+            torch.as_tensor(inv_mass_rows, **f).reshape(-1, 4).contiguous()
+        self.inv_mass_inst = None if inv_mass_inst is None else \
+            torch.as_tensor(inv_mass_inst, **f).reshape(-1, 2).contiguous()
+        self.logL, self.g_rows, self.g_inst = problem.loglik_grad(
+            self.layers, self.scale, self.bkg)
+
+    def native(self):
+        return _n.HmcState(*[_dp(t) for t in (
+            self.layers, self.scale, self.bkg, self.mom_rows, self.mom_inst, self.inv_mass_rows,
+            self.inv_mass_inst, self.logL, self.g_rows, self.g_inst)])
+
+
+class LeapfrogGraph:
+    """n leapfrog steps captured once in a HIP graph; launch() replays them."""
+
+    def __init__(self, problem, state, dt, n_steps):
+        self._problem, self._state = problem, state  # keep pointers alive
+        self._data = problem.values()
+        self._st = state.native()
+        ws = problem.workspace(NR_OP_LOGLIK_GRAD)
+        h = ctypes.c_void_p()
+        _n.check(_n.lib().nr_leapfrog_graph_create(
+            problem.plan.handle, ctypes.byref(self._data), ctypes.byref(self._st), dt, n_steps,
+            _dp(ws), ws.numel() * 8, ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _n.check(_n.lib().nr_graph_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _n.lib().nr_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _leapfrog(self, state, dt, n_steps, stream=None):
+    ws = self.workspace(NR_OP_LOGLIK_GRAD)
+    data = self.values()
+    st = state.native()
+    _n.check(_n.lib().nr_leapfrog(self.plan.handle, ctypes.byref(data), ctypes.byref(st), dt,
+                                  n_steps, _dp(ws), ws.numel() * 8, _stream(stream)))
+
+
+def _vi_elbo_grad(self, mu, omega, mask, eps, stream=None):
+    """ELBO estimate and its gradient w.r.t. (mu, omega); returns
+    (elbo, grad_mu, grad_omega, logL per sample)."""
+    import torch
+    dev = self.device
+    P = int(np.asarray(mu).size) if not hasattr(mu, "numel") else int(mu.numel())
+    f = dict(dtype=torch.float64, device=dev)
+    mu_t = torch.as_tensor(mu, **f).reshape(-1).contiguous()
+    om_t = torch.as_tensor(omega, **f).reshape(-1).contiguous()
+    mask_t = torch.as_tensor(mask, dtype=torch.uint8, device=dev).reshape(-1).contiguous()
+    eps_t = torch.as_tensor(eps, **f).reshape(-1).contiguous()
+    S = self.plan.n_items
+    if eps_t.numel() != S * P:
+        raise ValueError("eps must hold n_items x P draws")
+    out = dict(layers=torch.empty_like(self.layers), scale=torch.empty(S, **f),
+               bkg=torch.empty(S, **f), logL=torch.empty(S, **f),
+               g_rows=torch.empty_like(self.layers), g_inst=torch.empty(S, 2, **f),
+               grad_mu=torch.empty(P, **f), grad_omega=torch.empty(P, **f),
+               elbo=torch.empty(1, **f))
+    args = _n.ViArgs(_dp(mu_t), _dp(om_t), _dp(mask_t), _dp(eps_t), *[_dp(out[k]) for k in (
+        "layers", "scale", "bkg", "logL", "g_rows", "g_inst", "grad_mu", "grad_omega", "elbo")])
+    ws = self.workspace(NR_OP_LOGLIK_GRAD)
+    data = self.values()
+    _n.check(_n.lib().nr_vi_elbo_grad(self.plan.handle, ctypes.byref(data), ctypes.byref(args),
+                                      _dp(ws), ws.numel() * 8, _stream(stream)))
+    return out["elbo"], out["grad_mu"], out["grad_omega"], out["logL"]
+
+
+Problem.leapfrog = _leapfrog
+Problem.vi_elbo_grad = _vi_elbo_grad
+
+
+def tie_sum(first, src, values, stream=None):
+    """out[k] = sum_{t in [first[k], first[k+1])} values[src[t]] on the device."""
+    import torch
+    dev = values.device
+    first_t = torch.as_tensor(first, dtype=torch.int64, device=dev).contiguous()
+    src_t = torch.as_tensor(src, dtype=torch.int64, device=dev).contiguous()
+    vals = values.contiguous().reshape(-1)
+    out = torch.empty(first_t.numel() - 1, dtype=torch.float64, device=dev)
+    _n.check(_n.lib().nr_tie_sum(out.numel(), _dp(first_t), _dp(src_t), _dp(vals), _dp(out),
+                                 _stream(stream)))
+    return out
+
+
+def tie_map_to_csr(tie_of_entry, n_out):
+    """CSR (first, src) from an array giving, for every source entry, the
+    shared parameter it belongs to (or -1)."""
+    tie = np.asarray(tie_of_entry, np.int64).reshape(-1)
+    src = np.nonzero(tie >= 0)[0]
+    order = np.argsort(tie[src], kind="stable")
+    src = src[order]
+    counts = np.bincount(tie[src], minlength=n_out)
+    first = np.zeros(n_out + 1, np.int64)
+    first[1:] = np.cumsum(counts)
+    return first, src.astype(np.int64)
 
 
 def _make_autograd():

@@ -17,7 +17,9 @@ NR_SMEAR_NODES = 17
 # every symbol include/nr.h declares
 EXPORTS = ("nr_version", "nr_status_string", "nr_plan_create", "nr_plan_destroy",
            "nr_workspace_size", "nr_output_offsets", "nr_reflectivity", "nr_loglik",
-           "nr_loglik_grad", "nr_plan_set_timing_events")
+           "nr_loglik_grad", "nr_plan_set_timing_events", "nr_leapfrog",
+           "nr_leapfrog_graph_create", "nr_graph_launch", "nr_graph_destroy",
+           "nr_vi_elbo_grad", "nr_tie_sum")
 
 
 class BatchDesc(ctypes.Structure):
@@ -42,6 +44,18 @@ class Values(ctypes.Structure):
         ("bkg", ctypes.c_void_p),
         ("item_status", ctypes.c_void_p),
     ]
+
+
+class HmcState(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in (
+        "layers", "scale", "bkg", "mom_rows", "mom_inst", "inv_mass_rows", "inv_mass_inst",
+        "logL", "g_rows", "g_inst")]
+
+
+class ViArgs(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in (
+        "mu", "omega", "mask", "eps", "layers", "scale", "bkg", "logL", "g_rows", "g_inst",
+        "grad_mu", "grad_omega", "elbo")]
 
 
 class NativeError(RuntimeError):
@@ -82,6 +96,22 @@ def lib():
         L.nr_loglik_grad.argtypes = [P, ctypes.POINTER(Values), P, P, P, P, ctypes.c_size_t, P]
         L.nr_plan_set_timing_events.restype = ctypes.c_int32
         L.nr_plan_set_timing_events.argtypes = [P, P, P]
+        L.nr_leapfrog.restype = ctypes.c_int32
+        L.nr_leapfrog.argtypes = [P, ctypes.POINTER(Values), ctypes.POINTER(HmcState),
+                                  ctypes.c_double, ctypes.c_int32, P, ctypes.c_size_t, P]
+        L.nr_leapfrog_graph_create.restype = ctypes.c_int32
+        L.nr_leapfrog_graph_create.argtypes = [P, ctypes.POINTER(Values), ctypes.POINTER(HmcState),
+                                               ctypes.c_double, ctypes.c_int32, P,
+                                               ctypes.c_size_t, ctypes.POINTER(P)]
+        L.nr_graph_launch.restype = ctypes.c_int32
+        L.nr_graph_launch.argtypes = [P, P]
+        L.nr_graph_destroy.restype = ctypes.c_int32
+        L.nr_graph_destroy.argtypes = [P]
+        L.nr_vi_elbo_grad.restype = ctypes.c_int32
+        L.nr_vi_elbo_grad.argtypes = [P, ctypes.POINTER(Values), ctypes.POINTER(ViArgs), P,
+                                      ctypes.c_size_t, P]
+        L.nr_tie_sum.restype = ctypes.c_int32
+        L.nr_tie_sum.argtypes = [ctypes.c_int64, P, P, P, P, P]
         _lib = L
     return _lib
 

@@ -136,6 +136,8 @@ struct nr_plan {
   double* d_rule = nullptr;
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;
   std::vector<Launch> launches_fwd, launches_grad;
+  uint8_t* d_row_kind = nullptr;  // 0 fronting, 1 layer, 2 backing, per row
+  int uniform_rows = 0;           // rows per item if all items agree, else 0
   double node_t[kSmearNodes], node_w[kSmearNodes];
   std::vector<void*> owned;
 };
@@ -214,13 +216,16 @@ size_t op_doubles(const nr_plan* p, int op) {
   return n;
 }
 
-nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st) {
+nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st,
+                       bool events = true);
+
+nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st, bool events) {
   {
     hipError_t e = launch_item_consts(p->d_row_off, a.layers, const_cast<double*>(a.consts),
                                       p->n_items, st);
     if (e != hipSuccess) return hip_fail(e, "constants launch");
   }
-  if (p->ev_start) {
+  if (events && p->ev_start) {
     hipError_t e = hipEventRecord(p->ev_start, st);
     if (e != hipSuccess) return hip_fail(e, "timing event");
   }
@@ -236,14 +241,85 @@ nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st) {
                         : launch_forward(op, a, L.n_wu, st);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
   }
-  if (p->ev_stop) {
+  if (events && p->ev_stop) {
     hipError_t e = hipEventRecord(p->ev_stop, st);
     if (e != hipSuccess) return hip_fail(e, "timing event");
   }
   return NR_OK;
 }
 
+// Enqueues the whole logL + gradient evaluation (validated arguments).
+nr_status enqueue_grad(const nr_plan* p, const nr_values* v, double* logL, double* g_rows,
+                       double* g_inst, void* ws, hipStream_t s, bool events) {
+  KernelArgs a = base_args(p, v);
+  a.consts = static_cast<double*>(ws);
+  a.rec = static_cast<double*>(ws) + consts_doubles(p);
+  nr_status st = run_launches(p, kOpLoglikGrad, a, s, events);
+  if (st != NR_OK) return st;
+  ReduceArgs r;
+  std::memset(&r, 0, sizeof(r));
+  r.n_items = p->n_items;
+  r.item_wu_first = p->lists_grad.first;
+  r.item_wu_count = p->lists_grad.count;
+  r.rec_of_wu = p->lists_grad.offs;
+  r.rec = a.rec;
+  r.row_off = p->d_row_off;
+  r.layers = v->layers;
+  r.logL = logL;
+  r.g_rows = g_rows;
+  r.g_inst = g_inst;
+  hipError_t e = launch_reduce(kOpLoglikGrad, r, s);
+  return e == hipSuccess ? NR_OK : hip_fail(e, "reduce launch");
+}
+
+nr_status check_hmc(const nr_plan* p, const nr_values* data, const nr_hmc_state* st, double dt,
+                    int32_t n_steps, void* ws, size_t ws_bytes) {
+  if (!p || !data || !st || n_steps < 0 || !std::isfinite(dt)) return NR_EINVAL;
+  nr_values v = *data;
+  v.layers = st->layers;
+  v.scale = st->scale;
+  v.bkg = st->bkg;
+  nr_status s = check_call(p, &v, true);
+  if (s != NR_OK) return s;
+  if (p->n_items == 0) return NR_OK;
+  if (!st->mom_rows || !st->mom_inst || !st->logL || !st->g_rows || !st->g_inst)
+    return NR_EINVAL;
+  const size_t need = sizeof(double) * op_doubles(p, NR_OP_LOGLIK_GRAD);
+  if (need > 0 && (!ws || ws_bytes < need)) return NR_EWORKSPACE;
+  return NR_OK;
+}
+
+nr_status enqueue_leapfrog(const nr_plan* p, const nr_values* data, const nr_hmc_state* st,
+                           double dt, int32_t n_steps, void* ws, hipStream_t s, bool events) {
+  if (p->n_items == 0) return NR_OK;
+  nr_values v = *data;
+  v.layers = st->layers;
+  v.scale = st->scale;
+  v.bkg = st->bkg;
+  const int64_t nre = p->row_off.back() * 4;
+  const int64_t ni = p->n_items;
+  for (int32_t k = 0; k < n_steps; ++k) {
+    hipError_t e = launch_kick(nre, 2 * ni, st->mom_rows, st->g_rows, st->mom_inst, st->g_inst,
+                               0.5 * dt, s);
+    if (e != hipSuccess) return hip_fail(e, "kick launch");
+    e = launch_drift(nre, ni, p->d_row_kind, st->layers, st->scale, st->bkg, st->mom_rows,
+                     st->mom_inst, st->inv_mass_rows, st->inv_mass_inst, dt, s);
+    if (e != hipSuccess) return hip_fail(e, "drift launch");
+    nr_status r = enqueue_grad(p, &v, st->logL, st->g_rows, st->g_inst, ws, s, events);
+    if (r != NR_OK) return r;
+    e = launch_kick(nre, 2 * ni, st->mom_rows, st->g_rows, st->mom_inst, st->g_inst, 0.5 * dt, s);
+    if (e != hipSuccess) return hip_fail(e, "kick launch");
+  }
+  return NR_OK;
+}
+
 }  // namespace
+
+struct nr_graph {
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 extern "C" {
 
@@ -358,6 +434,16 @@ nr_status nr_plan_create(const nr_batch_desc* d, nr_plan** out) {
     if (e == hipSuccess) { e = upload(&L.count, count); keep(L.count); }
     if (e == hipSuccess) { e = upload(&L.offs, offs); keep(L.offs); }
   };
+  {
+    std::vector<uint8_t> kind((size_t)p->row_off.back(), 1);
+    p->uniform_rows = nI > 0 ? (int)(p->row_off[1] - p->row_off[0]) : 0;
+    for (int b = 0; b < nI; ++b) {
+      kind[(size_t)p->row_off[b]] = 0;
+      kind[(size_t)p->row_off[b + 1] - 1] = 2;
+      if (p->row_off[b + 1] - p->row_off[b] != p->uniform_rows) p->uniform_rows = 0;
+    }
+    if (e == hipSuccess) { e = upload(&p->d_row_kind, kind); keep(p->d_row_kind); }
+  }
   upload_lists(p->lists_ll, ll_first, ll_count, ll_offs);
   upload_lists(p->lists_grad, gr_first, gr_count, gr_offs);
   if (e == hipSuccess) {
@@ -457,6 +543,100 @@ nr_status nr_plan_create(const nr_batch_desc* d, nr_plan** out) {
   return NR_OK;
 }
 
+nr_status nr_leapfrog(const nr_plan* p, const nr_values* data, const nr_hmc_state* st, double dt,
+                      int32_t n_steps, void* ws, size_t ws_bytes, void* stream) {
+  nr_status s = check_hmc(p, data, st, dt, n_steps, ws, ws_bytes);
+  if (s != NR_OK) return s;
+  return enqueue_leapfrog(p, data, st, dt, n_steps, ws, (hipStream_t)stream, true);
+}
+
+nr_status nr_leapfrog_graph_create(const nr_plan* p, const nr_values* data, const nr_hmc_state* st,
+                                   double dt, int32_t n_steps, void* ws, size_t ws_bytes,
+                                   nr_graph** out) {
+  if (!out) return NR_EINVAL;
+  *out = nullptr;
+  nr_status s = check_hmc(p, data, st, dt, n_steps, ws, ws_bytes);
+  if (s != NR_OK) return s;
+  nr_graph* g = new nr_graph();
+  hipError_t e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete g;
+    return hip_fail(e, "graph stream");
+  }
+  e = hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    s = enqueue_leapfrog(p, data, st, dt, n_steps, ws, g->stream, false);
+    hipError_t e2 = hipStreamEndCapture(g->stream, &g->graph);
+    if (s == NR_OK && e2 != hipSuccess) s = hip_fail(e2, "end capture");
+  } else {
+    s = hip_fail(e, "begin capture");
+  }
+  if (s == NR_OK) {
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) s = hip_fail(e, "graph instantiate");
+  }
+  if (s != NR_OK) {
+    nr_graph_destroy(g);
+    return s;
+  }
+  *out = g;
+  return NR_OK;
+}
+
+nr_status nr_graph_launch(nr_graph* g, void* stream) {
+  if (!g || !g->exec) return NR_EINVAL;
+  hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  return e == hipSuccess ? NR_OK : hip_fail(e, "graph launch");
+}
+
+nr_status nr_graph_destroy(nr_graph* g) {
+  if (!g) return NR_OK;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->stream) (void)hipStreamDestroy(g->stream);
+  delete g;
+  return NR_OK;
+}
+
+nr_status nr_vi_elbo_grad(const nr_plan* p, const nr_values* data, const nr_vi_args* vi,
+                          void* ws, size_t ws_bytes, void* stream) {
+  if (!p || !data || !vi) return NR_EINVAL;
+  if (p->n_items == 0) return NR_EINVAL;
+  const int rows = p->uniform_rows;
+  if (rows < 2) return NR_EINVAL;
+  if (!vi->mu || !vi->omega || !vi->mask || !vi->eps || !vi->layers || !vi->scale ||
+      !vi->bkg || !vi->logL || !vi->g_rows || !vi->g_inst || !vi->grad_mu ||
+      !vi->grad_omega || !vi->elbo)
+    return NR_EINVAL;
+  nr_values v = *data;
+  v.layers = vi->layers;
+  v.scale = vi->scale;
+  v.bkg = vi->bkg;
+  nr_status s = check_call(p, &v, true);
+  if (s != NR_OK) return s;
+  const size_t need = sizeof(double) * op_doubles(p, NR_OP_LOGLIK_GRAD);
+  if (need > 0 && (!ws || ws_bytes < need)) return NR_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  const int P = rows * 4 + 2;
+  hipError_t e = launch_vi_sample(p->n_items, P, rows, vi->mu, vi->omega, vi->mask, vi->eps,
+                                  vi->layers, vi->scale, vi->bkg, st);
+  if (e != hipSuccess) return hip_fail(e, "sampler launch");
+  s = enqueue_grad(p, &v, vi->logL, vi->g_rows, vi->g_inst, ws, st, true);
+  if (s != NR_OK) return s;
+  e = launch_vi_reduce(p->n_items, P, rows, vi->omega, vi->mask, vi->eps, vi->logL, vi->g_rows,
+                       vi->g_inst, vi->grad_mu, vi->grad_omega, vi->elbo, st);
+  return e == hipSuccess ? NR_OK : hip_fail(e, "reduction launch");
+}
+
+nr_status nr_tie_sum(int64_t n_out, const int64_t* first, const int64_t* src, const double* in,
+                     double* out, void* stream) {
+  if (n_out < 0) return NR_EINVAL;
+  if (n_out == 0) return NR_OK;
+  if (!first || !src || !in || !out) return NR_EINVAL;
+  hipError_t e = launch_tie_sum(n_out, first, src, in, out, (hipStream_t)stream);
+  return e == hipSuccess ? NR_OK : hip_fail(e, "tie-sum launch");
+}
+
 nr_status nr_plan_set_timing_events(nr_plan* p, void* start, void* stop) {
   if (!p || ((start == nullptr) != (stop == nullptr))) return NR_EINVAL;
   p->ev_start = static_cast<hipEvent_t>(start);
@@ -531,26 +711,7 @@ nr_status nr_loglik_grad(const nr_plan* p, const nr_values* v, double* logL, dou
   if (!logL || !g_rows || !g_inst) return NR_EINVAL;
   const size_t need = sizeof(double) * op_doubles(p, NR_OP_LOGLIK_GRAD);
   if (need > 0 && (!ws || ws_bytes < need)) return NR_EWORKSPACE;
-  hipStream_t s = (hipStream_t)stream;
-  KernelArgs a = base_args(p, v);
-  a.consts = static_cast<double*>(ws);
-  a.rec = static_cast<double*>(ws) + consts_doubles(p);
-  st = run_launches(p, kOpLoglikGrad, a, s);
-  if (st != NR_OK) return st;
-  ReduceArgs r;
-  std::memset(&r, 0, sizeof(r));
-  r.n_items = p->n_items;
-  r.item_wu_first = p->lists_grad.first;
-  r.item_wu_count = p->lists_grad.count;
-  r.rec_of_wu = p->lists_grad.offs;
-  r.rec = a.rec;
-  r.row_off = p->d_row_off;
-  r.layers = v->layers;
-  r.logL = logL;
-  r.g_rows = g_rows;
-  r.g_inst = g_inst;
-  hipError_t e = launch_reduce(kOpLoglikGrad, r, s);
-  return e == hipSuccess ? NR_OK : hip_fail(e, "reduce launch");
+  return enqueue_grad(p, v, logL, g_rows, g_inst, ws, (hipStream_t)stream, true);
 }
 
 }  // extern "C"

@@ -90,4 +90,21 @@ hipError_t launch_forward(int op, const KernelArgs& a, int n_wu, hipStream_t st)
 hipError_t launch_grad(int bucket, bool tail, const KernelArgs& a, int n_wu, hipStream_t st);
 hipError_t launch_reduce(int op, const ReduceArgs& a, hipStream_t st);
 
+hipError_t launch_kick(int64_t n_row_entries, int64_t n_inst, double* mom_rows,
+                       const double* g_rows, double* mom_inst, const double* g_inst, double h,
+                       hipStream_t st);
+hipError_t launch_drift(int64_t n_row_entries, int64_t n_items, const uint8_t* row_kind,
+                        double* layers, double* scale, double* bkg, const double* mom_rows,
+                        const double* mom_inst, const double* im_rows, const double* im_inst,
+                        double dt, hipStream_t st);
+hipError_t launch_vi_sample(int64_t n_samples, int P, int rows, const double* mu,
+                            const double* omega, const uint8_t* mask, const double* eps,
+                            double* layers, double* scale, double* bkg, hipStream_t st);
+hipError_t launch_vi_reduce(int64_t n_samples, int P, int rows, const double* omega,
+                            const uint8_t* mask, const double* eps, const double* logL,
+                            const double* g_rows, const double* g_inst, double* grad_mu,
+                            double* grad_omega, double* elbo, hipStream_t st);
+hipError_t launch_tie_sum(int64_t n_out, const int64_t* first, const int64_t* src,
+                          const double* in, double* out, hipStream_t st);
+
 }  // namespace nr
