@@ -67,6 +67,28 @@ class _Hip:
         self.L.hipEventDestroy(e)
 
 
+KERNEL_SOURCES = ["paper_2509_06924_amd/csrc/nr_kernels.hip",
+                  "paper_2509_06924_amd/csrc/nr_device.hpp",
+                  "paper_2509_06924_amd/csrc/nr_internal.hpp"]
+
+
+def measured_traffic(workload):
+    """HBM bytes per step of the layer-product kernels from the committed
+    FETCH_SIZE / WRITE_SIZE summary (calibrated on a plain copy), or None when
+    there is none or the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if rec.get("kernel_sources_sha256") != h.hexdigest():
+        return None
+    return rec.get("traffic_bytes_per_step")
+
+
 def make_workload(name):
     from paper_2509_06924_amd import inputs
     if name == "c2":
@@ -219,7 +241,7 @@ def main():
             "peak": FP64_VALU_PEAK / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_VALU_PEAK,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload),
             "kernel": "k_loglik_grad (layer product, smearing, logL and adjoint)",
             "kernel_ms": kern_s * 1e3,
             "flop_per_layer_step": FLOP_PER_LAYER_STEP,
