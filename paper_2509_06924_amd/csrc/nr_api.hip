@@ -108,6 +108,23 @@ struct RecordLists {
   int64_t* offs = nullptr;
 };
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block b -> XCD b % 8)
+// and each XCD has its own L2.  Block b takes entry xcd_order(b, n) of the
+// cost-sorted unit list: within each chunk of 8 x kXcdRun blocks, one XCD
+// gets a run of kXcdRun consecutive entries (the units of one item are
+// consecutive), so an item's layer records are fetched into one L2, while
+// the chunks keep the longest-first order.  The last partial chunk maps to
+// itself.
+constexpr int kXcds = 8;
+constexpr size_t kXcdRun = 8;
+size_t xcd_order(size_t b, size_t n) {
+  const size_t chunk = kXcds * kXcdRun;
+  const size_t c0 = (b / chunk) * chunk;
+  if (c0 + chunk > n) return b;
+  const size_t r = b - c0;
+  return c0 + (r % kXcds) * kXcdRun + r / kXcds;
+}
+
 template <class T>
 hipError_t upload(T** dst, const std::vector<T>& src) {
   *dst = nullptr;
@@ -365,8 +382,9 @@ nr_status nr_plan_create(const nr_batch_desc* d, nr_plan** out) {
   // Forward ops: one unit per item x 64 points (the last may be partial),
   // one record (a logL partial) per unit.  Gradient op: full units as above
   // plus tail units that pack the trailing partial groups of items with the
-  // same depth and node count; a full unit writes one record, a tail lane
-  // writes its own.  Every item's records are listed contiguously.
+  // same depth and node count; a full unit writes one record, and so does
+  // each item's group of lanes in a tail unit.  Every item's records are
+  // listed contiguously.
   const int nI = d->n_items;
   p->out_off.assign(nI + 1, 0);
   struct Wu {
@@ -403,18 +421,17 @@ nr_status nr_plan_create(const nr_batch_desc* d, nr_plan** out) {
     const int nfull = (int)(nq / kWuPoints);
     const int ntail = (int)(nq % kWuPoints);
     gr_first[b] = (int64_t)gr_offs.size();
-    gr_count[b] = nfull + ntail;
+    gr_count[b] = nfull + (ntail > 0 ? 1 : 0);
     for (int k = 0; k < nfull; ++k) {
       grad_units[bk].push_back({b, k * kWuPoints, rec_gr, (double)kWuPoints * K * (N + 1)});
       gr_offs.push_back(rec_gr);
       rec_gr += rsz;
     }
     if (ntail > 0) {
+      // the tail's lanes sum into one record of the item
       tails[{N, K}].push_back({b, nfull * kWuPoints, ntail, rec_gr});
-      for (int t = 0; t < ntail; ++t) {
-        gr_offs.push_back(rec_gr);
-        rec_gr += rsz;
-      }
+      gr_offs.push_back(rec_gr);
+      rec_gr += rsz;
     }
   }
   p->rec_ll_total = rec_ll;
@@ -463,9 +480,10 @@ nr_status nr_plan_create(const nr_batch_desc* d, nr_plan** out) {
       std::vector<int32_t> it(v.size()), p0(v.size());
       std::vector<int64_t> rc(v.size());
       for (size_t k = 0; k < v.size(); ++k) {
-        it[k] = v[k].item;
-        p0[k] = v[k].p0;
-        rc[k] = v[k].rec;
+        const size_t src = xcd_order(k, v.size());
+        it[k] = v[src].item;
+        p0[k] = v[src].p0;
+        rc[k] = v[src].rec;
       }
       Launch L;
       L.bucket = bk;
@@ -507,7 +525,7 @@ nr_status nr_plan_create(const nr_batch_desc* d, nr_plan** out) {
         for (int l = 0; l < t.count; ++l) {
           b_litem[bk][base + fill[u] + l] = t.item;
           b_lpt[bk][base + fill[u] + l] = t.p0 + l;
-          b_lrec[bk][base + fill[u] + l] = t.rec0 + (int64_t)l * (3 + 4 * (kv.first.first + 2));
+          b_lrec[bk][base + fill[u] + l] = t.rec0;
         }
         fill[u] += t.count;
       }

@@ -203,9 +203,9 @@ __device__ __forceinline__ WuInfo wu_setup(const KernelArgs& a, int w, int lane)
 
 // Tail work units pack the last partial group of points of several items of
 // equal depth into one wave: lane l evaluates point tail_pt[l] of item
-// tail_item[l] and writes its own record at tail_rec[l] (idle lanes have
-// tail_rec = -1 and repeat lane 0's point).  The depth is wave-uniform and
-// taken from wu_item[w].
+// tail_item[l]; the lanes of one item are contiguous and share its tail
+// record offset tail_rec[l] (idle lanes have tail_rec = -1 and repeat lane
+// 0's point).  The depth is wave-uniform and taken from wu_item[w].
 __device__ __forceinline__ WuInfo tail_setup(const KernelArgs& a, int w, int lane) {
   WuInfo u;
   const int first = a.wu_item[w];
@@ -576,34 +576,55 @@ __global__ __launch_bounds__(64) void k_loglik_grad(KernelArgs a) {
   flag(a.item_status, u.item, bits);
 
   const int NR = N + 2;
+  const int nf = 3 + 4 * NR;
   if constexpr (TAIL) {
-    // one record per lane
-    if (u.active) {
-      double* rec = a.rec + a.tail_rec[(int64_t)w * 64 + lane];
-      rec[0] = ll;
-      rec[1] = gsc;
-      rec[2] = gbk;
+    // Lanes of one item are contiguous; idle lanes (key -1) follow the last
+    // item.  A segmented inclusive scan over the lanes leaves each item's
+    // sums in its last lane, which writes the item's tail record.
+    const int key = u.active ? u.item : -1;
+    bool take[6];
 #pragma unroll
-      for (int m = 0; m < LMAX + 2; ++m) {
-        if (m < NR) {
-          rec[3 + m] = fac * acc.Hw[m].re;
-          rec[3 + NR + m] = fac * acc.Hw[m].im;
-          rec[3 + 2 * NR + m] = fac * acc.Hd[m];
-          rec[3 + 3 * NR + m] = fac * acc.Hs[m];
-        }
+    for (int s6 = 0; s6 < 6; ++s6) {
+      const int off = 1 << s6;
+      // every lane takes part in the shuffle (it must not sit behind the
+      // lane test, which would leave its source lanes inactive)
+      const int kp = __shfl_up(key, off, 64);
+      take[s6] = (lane >= off) && (kp == key);
+    }
+    const int key_next = __shfl_down(key, 1, 64);
+    const bool writer = u.active && (lane == 63 || key_next != key);
+    double* rec = a.rec + a.tail_rec[(int64_t)w * 64 + lane];
+    auto seg_put = [&](int f, double v) {
+#pragma unroll
+      for (int s6 = 0; s6 < 6; ++s6) {
+        const double o = __shfl_up(v, 1 << s6, 64);
+        if (take[s6]) v += o;
+      }
+      if (writer) rec[f] = v;
+    };
+    seg_put(0, ll);
+    seg_put(1, gsc);
+    seg_put(2, gbk);
+#pragma unroll
+    for (int m = 0; m < LMAX + 2; ++m) {
+      if (m < NR) {
+        seg_put(3 + m, fac * acc.Hw[m].re);
+        seg_put(3 + NR + m, fac * acc.Hw[m].im);
+        seg_put(3 + 2 * NR + m, fac * acc.Hd[m]);
+        seg_put(3 + 3 * NR + m, fac * acc.Hs[m]);
       }
     }
     return;
   }
-  // ---- wave reduction and record ----
-  double* rec = a.rec + a.wu_rec[w];
+  // ---- wave reduction; the sums go through LDS into one coalesced store ----
+  __shared__ double stage[3 + 4 * (LMAX + 2)];
   ll = wave_sum(ll);
   gsc = wave_sum(gsc);
   gbk = wave_sum(gbk);
   if (lane == 0) {
-    rec[0] = ll;
-    rec[1] = gsc;
-    rec[2] = gbk;
+    stage[0] = ll;
+    stage[1] = gsc;
+    stage[2] = gbk;
   }
 #pragma unroll
   for (int m = 0; m < LMAX + 2; ++m) {
@@ -613,13 +634,16 @@ __global__ __launch_bounds__(64) void k_loglik_grad(KernelArgs a) {
       const double dd = wave_sum(fac * acc.Hd[m]);
       const double ss = wave_sum(fac * acc.Hs[m]);
       if (lane == 0) {
-        rec[3 + m] = wr;
-        rec[3 + NR + m] = wi;
-        rec[3 + 2 * NR + m] = dd;
-        rec[3 + 3 * NR + m] = ss;
+        stage[3 + m] = wr;
+        stage[3 + NR + m] = wi;
+        stage[3 + 2 * NR + m] = dd;
+        stage[3 + 3 * NR + m] = ss;
       }
     }
   }
+  __syncthreads();
+  double* rec = a.rec + a.wu_rec[w];
+  for (int f = lane; f < nf; f += 64) rec[f] = stage[f];
 }
 
 // ---------------------------------------------------------------------------
