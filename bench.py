@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("logL+∇ evals/s (sample×Q×layer), FP64 vs plain; % of FP64 VALU peak")
 UNIT = "layer-steps/s"
 FP64_VALU_PEAK = 78.6e12  # MI355X dense FP64 vector, FLOP/s
+FP32_VALU_PEAK = 157.3e12  # MI355X FP32 vector (counts packed FP32), FLOP/s
 
 # Algorithmic FP64 operations per layer-step of the forward + reverse sweep
 # (operation count of the method; FMA = 2; special functions at fixed costs:
@@ -67,7 +68,8 @@ class _Hip:
         self.L.hipEventDestroy(e)
 
 
-KERNEL_SOURCES = ["paper_2509_06924_amd/csrc/nr_kernels.hip",
+KERNEL_SOURCES = ["paper_2509_06924_amd/csrc/nr_kernels.hpp",
+                  "paper_2509_06924_amd/csrc/nr_kernels_f64.hip",
                   "paper_2509_06924_amd/csrc/nr_device.hpp",
                   "paper_2509_06924_amd/csrc/nr_internal.hpp"]
 
@@ -250,6 +252,7 @@ def main():
     if not args.no_extra_rows:
         rec["forward_only"] = forward_only_row(prob, batch, args.steps)
         rec["plain_unbatched"] = plain_unbatched_row(nr, batch)
+        rec["fp32"] = fp32_row(nr, batch, out, args.steps, hip)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
     print(json.dumps(rec), flush=True)
@@ -268,6 +271,58 @@ def forward_only_row(prob, batch, steps):
     dt = (time.perf_counter() - t0) / steps
     return {"value": batch.layer_steps() / dt, "unit": UNIT, "ms_per_step": dt * 1e3,
             "what": "nr_loglik on the same batch (forward only)"}
+
+
+def fp32_row(nr, batch, out64, steps, hip):
+    """The FP32 variant on the same workload: time, rate, fraction of the FP32
+    VALU peak, and its largest deviation from the FP64 path (which matches the
+    oracle to 1e-10 / 1e-8), over every item."""
+    import numpy as np
+    import torch
+
+    from paper_2509_06924_amd import _native
+    prob = nr.Problem.from_batch(batch, device="cuda:0", precision=nr.NR_F32)
+    out = (torch.empty_like(out64[0]), torch.empty_like(out64[1]), torch.empty_like(out64[2]))
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        prob.loglik_grad(out=out, stream=stream)
+    torch.cuda.synchronize()
+    L = _native.lib()
+    evs = [(hip.event(), hip.event()) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        _native.check(L.nr_plan_set_timing_events(prob.plan.handle, evs[k][0], evs[k][1]))
+        prob.loglik_grad(out=out, stream=stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    _native.check(L.nr_plan_set_timing_events(prob.plan.handle, None, None))
+    kern_s = sum(hip.elapsed_ms(a, b) for a, b in evs) / len(evs) / 1e3
+    for a, b in evs:
+        hip.destroy(a)
+        hip.destroy(b)
+    ll32, ll64 = out[0].cpu().numpy(), out64[0].cpu().numpy()
+    units = np.array([1.0, 1e-6, 1e-6, 1.0])
+    g32 = out[1].cpu().numpy() * units
+    g64 = out64[1].cpu().numpy() * units
+    i32 = out[2].cpu().numpy() * np.array([1.0, 1e-7])
+    i64 = out64[2].cpu().numpy() * np.array([1.0, 1e-7])
+    gerr = 0.0
+    for b in range(batch.n_items):
+        r0, r1 = batch.row_off[b], batch.row_off[b + 1]
+        a = np.concatenate([g32[r0:r1].ravel(), i32[b]])
+        o = np.concatenate([g64[r0:r1].ravel(), i64[b]])
+        gerr = max(gerr, float(np.max(np.abs(a - o)) / np.max(np.abs(o))))
+    achieved = FLOP_PER_LAYER_STEP * batch.layer_steps() / kern_s
+    return {"value": batch.layer_steps() / dt, "unit": UNIT, "ms_per_step": dt * 1e3,
+            "kernel_ms": kern_s * 1e3, "dtype": "f32",
+            "achieved_tflops": achieved / 1e12, "peak_tflops": FP32_VALU_PEAK / 1e12,
+            "frac": achieved / FP32_VALU_PEAK,
+            "max_rel_err_logL": float(np.max(np.abs(ll32 - ll64) / np.abs(ll64))),
+            "max_rel_err_grad": gerr,
+            "what": "nr_loglik_grad with NR_F32 (layer product and adjoint in float; "
+                    "kz0^2 - 4 pi drho, smearing, chi^2 and accumulation in FP64); errors "
+                    "against the FP64 path over every item, gradient in natural units "
+                    "relative to each item's largest component"}
 
 
 def plain_unbatched_row(nr, batch, n_items=64):

@@ -70,8 +70,12 @@ typedef int32_t nr_status;
 #define NR_EHIP 3       /* a HIP runtime call or kernel launch failed */
 #define NR_ENOMEM 4     /* plan creation could not allocate device memory */
 
-/* Arithmetic precision of the bulk layer product.  The wavevector root,
- * quadrature, smearing sums, chi^2 and gradient accumulation stay FP64. */
+/* Arithmetic precision of the bulk layer product (wavevector roots, interface
+ * coefficients, phases, the 2x2 product and its adjoint).  In both, the
+ * quadrature nodes, the critical-edge difference kz0^2 - 4 pi (rho_j - rho_0),
+ * the smearing sums, chi^2, the likelihood seeds and the per-point gradient
+ * accumulation are FP64; NR_F32 rounds that difference to float once and
+ * takes the root in float.  Inputs and outputs are FP64 arrays either way. */
 #define NR_F64 0
 #define NR_F32 1
 
@@ -126,7 +130,7 @@ nr_status nr_plan_create(const nr_batch_desc* desc, nr_plan** plan_out);
 nr_status nr_plan_destroy(nr_plan* plan);
 
 /* Bytes of caller-provided device workspace that `op` needs for this plan:
- * 48 bytes per row of every item (per-layer constants) plus, for NR_OP_LOGLIK
+ * 80 bytes per row of every item (per-layer constants) plus, for NR_OP_LOGLIK
  * and NR_OP_LOGLIK_GRAD, the per-work-unit partial sums.  Any 8-byte aligned
  * device buffer of at least that size; contents need no initialisation and
  * are overwritten by every call.  Returns NR_EINVAL for an unknown op or a

@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libnr.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["nr_api.hip", "nr_kernels.hip", "nr_integrators.hip"]
+SOURCES = ["nr_api.hip", "nr_kernels_f64.hip", "nr_kernels_f32.hip", "nr_integrators.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

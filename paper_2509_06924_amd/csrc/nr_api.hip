@@ -223,8 +223,14 @@ KernelArgs base_args(const nr_plan* p, const nr_values* v) {
 }
 
 // Workspace layout: per-row layer records (6 doubles per row of every item),
-// then the per-work-unit partial records of the operation.
-size_t consts_doubles(const nr_plan* p) { return (size_t)p->row_off.back() * 6; }
+// their float copies (8 floats per row), then the per-work-unit partial
+// records of the operation.
+size_t consts_doubles(const nr_plan* p) {
+  return (size_t)p->row_off.back() * (kRecDoubles + kRecFloats / 2);
+}
+const float* consts_floats(const nr_plan* p, const double* ws) {
+  return reinterpret_cast<const float*>(ws + (size_t)p->row_off.back() * kRecDoubles);
+}
 
 size_t op_doubles(const nr_plan* p, int op) {
   size_t n = consts_doubles(p);
@@ -239,7 +245,7 @@ nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st,
 nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st, bool events) {
   {
     hipError_t e = launch_item_consts(p->d_row_off, a.layers, const_cast<double*>(a.consts),
-                                      p->n_items, st);
+                                      const_cast<float*>(a.constsf), p->n_items, st);
     if (e != hipSuccess) return hip_fail(e, "constants launch");
   }
   if (events && p->ev_start) {
@@ -254,8 +260,8 @@ nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st, b
     a.tail_item = L.lane_item;
     a.tail_pt = L.lane_pt;
     a.tail_rec = L.lane_rec;
-    hipError_t e = grad ? launch_grad(L.bucket, L.tail, a, L.n_wu, st)
-                        : launch_forward(op, a, L.n_wu, st);
+    hipError_t e = grad ? launch_grad(p->precision, L.bucket, L.tail, a, L.n_wu, st)
+                        : launch_forward(p->precision, op, a, L.n_wu, st);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
   }
   if (events && p->ev_stop) {
@@ -270,6 +276,7 @@ nr_status enqueue_grad(const nr_plan* p, const nr_values* v, double* logL, doubl
                        double* g_inst, void* ws, hipStream_t s, bool events) {
   KernelArgs a = base_args(p, v);
   a.consts = static_cast<double*>(ws);
+  a.constsf = consts_floats(p, a.consts);
   a.rec = static_cast<double*>(ws) + consts_doubles(p);
   nr_status st = run_launches(p, kOpLoglikGrad, a, s, events);
   if (st != NR_OK) return st;
@@ -692,6 +699,7 @@ nr_status nr_reflectivity(const nr_plan* p, const nr_values* v, double* r_hat, v
   KernelArgs a = base_args(p, v);
   a.out = r_hat;
   a.consts = static_cast<double*>(ws);
+  a.constsf = consts_floats(p, a.consts);
   return run_launches(p, kOpReflectivity, a, (hipStream_t)stream);
 }
 
@@ -706,6 +714,7 @@ nr_status nr_loglik(const nr_plan* p, const nr_values* v, double* logL, void* ws
   hipStream_t s = (hipStream_t)stream;
   KernelArgs a = base_args(p, v);
   a.consts = static_cast<double*>(ws);
+  a.constsf = consts_floats(p, a.consts);
   a.rec = static_cast<double*>(ws) + consts_doubles(p);
   st = run_launches(p, kOpLoglik, a, s);
   if (st != NR_OK) return st;

@@ -1,5 +1,5 @@
 // Device-side complex arithmetic and the special functions of the layer
-// product, for gfx950.  Everything here is FP64.
+// product, for gfx950: the FP64 path and the FP32 variant.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,34 +11,53 @@ constexpr double kFourPi = 12.566370614359172;
 constexpr double kHalfLn2Pi = 0.91893853320467274;
 constexpr double kFwhmPerSigma = 2.3548200450309493;
 
-struct cd {
-  double re, im;
+// Complex numbers of either precision (the FP64 path uses cd, the FP32
+// variant's layer product cf).  Mixed-precision expressions do not compile,
+// so a float computation cannot silently widen to double.
+template <class T>
+struct cx {
+  T re, im;
 };
+using cd = cx<double>;
+using cf = cx<float>;
 
-__device__ __forceinline__ cd mk(double a, double b) {
-  cd z;
+template <class T>
+__device__ __forceinline__ cx<T> mk(T a, T b) {
+  cx<T> z;
   z.re = a;
   z.im = b;
   return z;
 }
-__device__ __forceinline__ cd operator+(cd a, cd b) { return mk(a.re + b.re, a.im + b.im); }
-__device__ __forceinline__ cd operator-(cd a, cd b) { return mk(a.re - b.re, a.im - b.im); }
-__device__ __forceinline__ cd operator-(cd a) { return mk(-a.re, -a.im); }
-__device__ __forceinline__ cd operator*(cd a, cd b) {
+template <class T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return mk(a.re + b.re, a.im + b.im); }
+template <class T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return mk(a.re - b.re, a.im - b.im); }
+template <class T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a) { return mk(-a.re, -a.im); }
+template <class T>
+__device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
   return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
 }
-__device__ __forceinline__ cd operator*(double s, cd a) { return mk(s * a.re, s * a.im); }
-__device__ __forceinline__ cd& operator+=(cd& a, cd b) {
+template <class T>
+__device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return mk(s * a.re, s * a.im); }
+template <class T>
+__device__ __forceinline__ cx<T>& operator+=(cx<T>& a, cx<T> b) {
   a.re += b.re;
   a.im += b.im;
   return a;
 }
-__device__ __forceinline__ cd cconj(cd a) { return mk(a.re, -a.im); }
+template <class T>
+__device__ __forceinline__ cx<T> cconj(cx<T> a) { return mk(a.re, -a.im); }
 // conj(a) * b
-__device__ __forceinline__ cd cmulc(cd a, cd b) {
+template <class T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
   return mk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
 }
-__device__ __forceinline__ double cabs2(cd a) { return a.re * a.re + a.im * a.im; }
+template <class T>
+__device__ __forceinline__ T cabs2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+__device__ __forceinline__ cd widen(cd a) { return a; }
+__device__ __forceinline__ cd widen(cf a) { return mk((double)a.re, (double)a.im); }
+
 // 1/x from the hardware estimate v_rcp_f64 refined by two Newton steps
 // r <- r + r (1 - x r); each step squares the relative error.
 __device__ __forceinline__ double rcp(double x) {
@@ -172,10 +191,12 @@ __device__ __forceinline__ double kz0_squared(double q) {
 // A zero y with x < 0 gives (0, -sqrt|x|) whatever the sign of that zero.
 // |w|^2 gets 1e-300 added, which changes nothing unless w = 0 exactly, where
 // it yields kz of order 1e-75 instead of 0 (and keeps every value finite).
-struct Root {
-  cd kz;
-  double inv_abs2;
+template <class T>
+struct RootT {
+  cx<T> kz;
+  T inv_abs2;
 };
+using Root = RootT<double>;
 __device__ __forceinline__ Root kz_root(double x, double y) {
   const double a = fma(x, x, fma(y, y, 1e-300));
   const double ra = rsq(a);
@@ -187,6 +208,57 @@ __device__ __forceinline__ Root kz_root(double x, double y) {
   Root out;
   out.kz.re = (x >= 0.0) ? t : -o;
   out.kz.im = (x >= 0.0) ? o : -t;
+  out.inv_abs2 = ra;
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 variant.  The hardware transcendentals of gfx950 are used directly:
+// v_rcp_f32, v_rsq_f32 (about 1 ulp), v_exp_f32 (2^x), v_sin_f32 and
+// v_cos_f32 (of 2 pi x, for |x| <= 256; the argument is reduced to
+// [-1/2, 1/2] revolutions first).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ cf crecip(cf z) {
+  const float inv = __builtin_amdgcn_rcpf(z.re * z.re + z.im * z.im);
+  return mk(z.re * inv, -z.im * inv);
+}
+
+__device__ __forceinline__ float exp_f32(float x) {
+  constexpr float kLog2e = 1.44269504088896341f;
+  return __builtin_amdgcn_exp2f(x * kLog2e);
+}
+
+__device__ __forceinline__ void sincos_f32(float x, float* sn, float* cs) {
+  constexpr float kInv2Pi = 0.159154943091895336f;
+  float u = x * kInv2Pi;
+  u = u - __builtin_rintf(u);
+  *sn = __builtin_amdgcn_sinf(u);
+  *cs = __builtin_amdgcn_cosf(u);
+}
+
+// Complex exponential in FP32 (the LDS tables are not used).
+__device__ __forceinline__ cf cexp_tab(const MathTables&, cf z) {
+  float s, c;
+  sincos_f32(z.im, &s, &c);
+  const float e = exp_f32(z.re);
+  return mk(e * c, e * s);
+}
+
+// The FP32 root of w = x + i y, same branch and formulas as kz_root(double,
+// double); x is the FP64 difference kz0^2 - A rounded once to float, so the
+// cancellation near a critical edge happens in FP64.  |w|^2 gets 1e-36 added
+// (a floor of 1e-18 on |w|), which keeps w = 0 finite.
+__device__ __forceinline__ RootT<float> kz_root(float x, float y) {
+  const float a = fmaf(x, x, fmaf(y, y, 1e-36f));
+  const float ra = __builtin_amdgcn_rsqf(a);
+  const float m = a * ra;
+  const float h = 0.5f * (m + fabsf(x));
+  const float rh = __builtin_amdgcn_rsqf(h);
+  const float t = h * rh;
+  const float o = 0.5f * (y * rh);
+  RootT<float> out;
+  out.kz.re = (x >= 0.0f) ? t : -o;
+  out.kz.im = (x >= 0.0f) ? o : -t;
   out.inv_abs2 = ra;
   return out;
 }

@@ -13,8 +13,14 @@ constexpr int kSmearNodes = NR_SMEAR_NODES;
 constexpr int kMaxLayers = NR_MAX_LAYERS;
 constexpr int kWuPoints = 64;  // data points per work unit (one per lane)
 // Deepest stack whose gradient kernel keeps the per-level state and phases
-// in LDS (3 x 16 B x 64 lanes per level); deeper stacks recompute them.
+// in LDS (3 x 16 B x 64 lanes per level in FP64, 3 x 8 B in FP32); deeper
+// stacks recompute them.
 constexpr int kStoreMaxLayers = 10;
+constexpr int kStoreMaxLayersF32 = 10;
+// Per-row layer records in the workspace: 6 doubles, then (in a second
+// array) 8 floats.
+constexpr int kRecDoubles = 6;
+constexpr int kRecFloats = 8;
 
 constexpr uint32_t kItemNonfinite = NR_ITEM_NONFINITE;
 constexpr uint32_t kItemBadQ = NR_ITEM_BAD_Q;
@@ -64,6 +70,7 @@ struct KernelArgs {
   double* out;     // nr_reflectivity
   double* rec;     // workspace records
   const double* consts;  // workspace: per-item layer records (6 doubles per row)
+  const float* constsf;  // workspace: their float copies (8 floats per row)
   // plan-owned constants (device): quadrature node offsets in units of
   // sigma_Q and normalised weights (kSmearNodes each), then the tables
   // (sin, cos)(k pi/32) for k = 0..63 interleaved and 2^(j/64), j = 0..63
@@ -85,9 +92,13 @@ struct ReduceArgs {
 };
 
 hipError_t launch_item_consts(const int64_t* row_off, const double* layers, double* rec,
-                              int n_items, hipStream_t st);
-hipError_t launch_forward(int op, const KernelArgs& a, int n_wu, hipStream_t st);
-hipError_t launch_grad(int bucket, bool tail, const KernelArgs& a, int n_wu, hipStream_t st);
+                              float* recf, int n_items, hipStream_t st);
+// precision: NR_F64 or NR_F32
+hipError_t launch_forward(int precision, int op, const KernelArgs& a, int n_wu, hipStream_t st);
+hipError_t launch_grad(int precision, int bucket, bool tail, const KernelArgs& a, int n_wu,
+                       hipStream_t st);
+hipError_t launch_forward_f32(int op, const KernelArgs& a, int n_wu, hipStream_t st);
+hipError_t launch_grad_f32(int bucket, bool tail, const KernelArgs& a, int n_wu, hipStream_t st);
 hipError_t launch_reduce(int op, const ReduceArgs& a, hipStream_t st);
 
 hipError_t launch_kick(int64_t n_row_entries, int64_t n_inst, double* mom_rows,

@@ -1,27 +1,36 @@
 // HIP kernels for gfx950: Abeles reflectivity with Nevot-Croce roughness,
 // Gaussian resolution smearing, instrument scale/background, Gaussian
-// log-likelihood, and the hand-written adjoint of the whole chain.
+// log-likelihood, and the hand-written adjoint of the whole chain.  One
+// source for both precisions: a policy P (F64 or F32) sets the type of the
+// layer product; the quadrature nodes, kz0^2 - 4 pi drho, the smearing sums,
+// chi^2, the seeds and the per-point gradient accumulators are FP64 in both.
 //
 // Work decomposition: one work unit (WU) = one item x up to 64 consecutive data
 // points of its dataset, one wave (64 lanes) per WU, lane = data point.  The
 // item is wave-uniform, so its per-layer constants (precomputed per item by a
-// small prologue kernel) are read with scalar loads into scalar registers.  A lane walks all quadrature nodes of its point; for
-// each node it runs the layer product bottom-up (substrate -> surface), then
-// the adjoint top down, and accumulates w_k dR(q_k)/d(theta) in registers;
-// the point's likelihood seed multiplies the accumulators once at the end.
+// small prologue kernel) are read with scalar loads into scalar registers.  A
+// lane walks all quadrature nodes of its point; for each node it runs the
+// layer product bottom-up (substrate -> surface), then the adjoint top down,
+// and accumulates w_k dR(q_k)/d(theta) in registers; the point's likelihood
+// seed multiplies the accumulators once at the end.
 //
 // The layer product is written in a scaled form: the Abeles column
 // v_j = C_j v_{j+1} is divided by E_j at every layer, which leaves r = v1/v0
 // unchanged and turns the phase factor into e_j = E_j^-2 = exp(-2 i kz_j d_j),
 // whose modulus is <= 1 on the chosen branch (Im kz <= 0):
 //   P <- P + r'_j Qv,   Qv <- e_j (r'_j P + Qv),   starting from (1, 0).
+// The state therefore stays bounded (|P| <= prod (1 + |r'_j|)) and needs no
+// rescaling in FP32 either.
 //
 // Two gradient variants (one source, selected by template):
 //   store     - the forward sweep keeps each level's state (P, Qv) and phase
 //               e_j in LDS and each medium's kz_j, 1/|kz_j|^2 and interface
 //               coefficients in registers; the adjoint recomputes nothing.
 //   recompute - for deep stacks: the state tape stays in registers and the
-//               adjoint recomputes every layer's wavevector and phase.
+//               adjoint recomputes every layer's wavevector, interface
+//               coefficients and phase.
+#pragma once
+
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -32,68 +41,60 @@
 
 namespace nr {
 
+// Precision policies of the layer product.
+struct F64 {
+  using real = double;
+  static constexpr int kStoreMax = kStoreMaxLayers;
+};
+struct F32 {
+  using real = float;
+  static constexpr int kStoreMax = kStoreMaxLayersF32;
+};
+
 // ---------------------------------------------------------------------------
-// Per-item layer records, written by k_item_consts into the workspace (six
-// doubles per medium m = 0..N+1, indexed like the item's rows) and read by the
-// main kernels with scalar loads, since every lane of a wave uses the same
-// item:
+// Per-item layer records, written by k_item_consts into the workspace and
+// read by the main kernels with scalar loads, since every lane of a wave uses
+// the same item.  Per medium m = 0..N+1 (indexed like the item's rows), six
+// doubles:
 //   A  = 4 pi (rho_re,m - rho_re,0)        (0 for the fronting medium)
 //   B  = 4 pi |rho_im,m|                   (0 for the fronting: lossless)
 //   Nr + i Ni = w_m - w_{m+1} = (A_{m+1} - A_m) + i (B_{m+1} - B_m), the
 //        Q-independent numerator of r_m = (w_m - w_{m+1}) / (kz_m + kz_{m+1})^2
 //   C  = -2 sigma_{m+1}^2                  (Nevot-Croce exponent factor)
 //   D  = 2 d_m                             (layers 1..N)
+// and eight floats: B, Nr, Ni, C, D rounded to float, then padding (the FP32
+// variant reads A from the doubles: kz0^2 - A is formed in FP64).
 // Interface fields of the backing record are 0.
 // ---------------------------------------------------------------------------
-constexpr int kRec = 6;
-
-struct Layers {
-  const double* rec;  // the item's records
-  int z;              // an opaque zero (see opaque_zero)
-  __device__ __forceinline__ double at(int m, int f) const { return rec[(m + z) * kRec + f]; }
-  __device__ __forceinline__ double A(int m) const { return at(m, 0); }
-  __device__ __forceinline__ double B(int m) const { return at(m, 1); }
-  __device__ __forceinline__ double Nr(int m) const { return at(m, 2); }
-  __device__ __forceinline__ double Ni(int m) const { return at(m, 3); }
-  __device__ __forceinline__ double C(int m) const { return at(m, 4); }
-  __device__ __forceinline__ double D(int m) const { return at(m, 5); }
-};
+constexpr int kRec = kRecDoubles;
+constexpr int kRecF = kRecFloats;
 
 // Layer records are indexed with (m + z) where z = k & KernelArgs::zero_mask
 // (the mask is 0): z is 0 at run time but varies with the node counter k as
 // far as the compiler can tell, so the records are re-read (with scalar
 // loads) inside the node loop instead of being hoisted out of it, which would
 // need far more scalar registers than exist.
-
-// One block of 64 per item, one lane per medium.
-__global__ __launch_bounds__(64) void k_item_consts(const int64_t* row_off, const double* layers,
-                                                    double* rec, int n_items) {
-  const int b = blockIdx.x;
-  const int m = threadIdx.x;
-  if (b >= n_items) return;
-  const int64_t r0 = row_off[b];
-  const int NR = (int)(row_off[b + 1] - r0);
-  if (m >= NR) return;
-  const double* rows = layers + 4 * r0;
-  const double rho0 = rows[1];
-  auto Af = [&](int j) { return (j == 0) ? 0.0 : kFourPi * (rows[4 * j + 1] - rho0); };
-  auto Bf = [&](int j) { return (j == 0) ? 0.0 : kFourPi * fabs(rows[4 * j + 2]); };
-  double* out = rec + (r0 + m) * kRec;
-  const double A = Af(m), B = Bf(m);
-  out[0] = A;
-  out[1] = B;
-  if (m + 1 < NR) {
-    const double sg = rows[4 * (m + 1) + 3];
-    out[2] = Af(m + 1) - A;
-    out[3] = Bf(m + 1) - B;
-    out[4] = -2.0 * (sg * sg);
-  } else {
-    out[2] = 0.0;
-    out[3] = 0.0;
-    out[4] = 0.0;
+template <class P>
+struct Layers {
+  using Re = typename P::real;
+  static constexpr bool kF64 = std::is_same<Re, double>::value;
+  const double* rec;   // the item's double records
+  const float* recf;   // the item's float records
+  int z;               // an opaque zero
+  __device__ __forceinline__ double at(int m, int f) const { return rec[(m + z) * kRec + f]; }
+  __device__ __forceinline__ Re get(int m, int fd, int ff) const {
+    if constexpr (kF64)
+      return at(m, fd);
+    else
+      return recf[(m + z) * kRecF + ff];
   }
-  out[5] = 2.0 * rows[4 * m];
-}
+  __device__ __forceinline__ double A(int m) const { return at(m, 0); }
+  __device__ __forceinline__ Re B(int m) const { return get(m, 1, 0); }
+  __device__ __forceinline__ Re Nr(int m) const { return get(m, 2, 1); }
+  __device__ __forceinline__ Re Ni(int m) const { return get(m, 3, 2); }
+  __device__ __forceinline__ Re C(int m) const { return get(m, 4, 3); }
+  __device__ __forceinline__ Re D(int m) const { return get(m, 5, 4); }
+};
 
 // The quadrature rule and the exp/sincos tables, staged per block in LDS.
 struct Shared {
@@ -120,21 +121,23 @@ __device__ __forceinline__ void stage_shared(Shared& s, int lane, const double* 
 }
 
 // Interface quantities shared by the forward and adjoint sweeps.
+template <class Re>
 struct Iface {
-  cd s;   // 1/(kz_j + kz_{j+1})
-  cd r;   // Fresnel coefficient
-  cd f;   // Nevot-Croce factor
-  cd rp;  // r f
-  cd kk;  // kz_j kz_{j+1}
+  cx<Re> s;   // 1/(kz_j + kz_{j+1})
+  cx<Re> r;   // Fresnel coefficient
+  cx<Re> f;   // Nevot-Croce factor
+  cx<Re> rp;  // r f
+  cx<Re> kk;  // kz_j kz_{j+1}
 };
 
-__device__ __forceinline__ Iface interface_coeffs(const MathTables& T, cd kzc, cd kzn, double Nr,
-                                                  double Ni, double C) {
-  Iface o;
+template <class Re>
+__device__ __forceinline__ Iface<Re> interface_coeffs(const MathTables& T, cx<Re> kzc, cx<Re> kzn,
+                                                      Re Nr, Re Ni, Re C) {
+  Iface<Re> o;
   o.s = crecip(kzc + kzn);
-  const cd s2 = o.s * o.s;
+  const cx<Re> s2 = o.s * o.s;
   // identical media: r = 0 exactly (also avoids 0 * inf when both kz vanish)
-  o.r = (Nr == 0.0 && Ni == 0.0) ? mk(0.0, 0.0) : mk(Nr, Ni) * s2;
+  o.r = (Nr == Re(0) && Ni == Re(0)) ? mk(Re(0), Re(0)) : mk(Nr, Ni) * s2;
   o.kk = kzc * kzn;
   o.f = cexp_tab(T, C * o.kk);
   o.rp = o.r * o.f;
@@ -142,38 +145,52 @@ __device__ __forceinline__ Iface interface_coeffs(const MathTables& T, cd kzc, c
 }
 
 // e_j = exp(-2 i kz_j d_j) = exp(D Im kz) cis(-D Re kz), D = 2 d_j.
-__device__ __forceinline__ cd layer_phase(const MathTables& T, cd kz, double D) {
+template <class Re>
+__device__ __forceinline__ cx<Re> layer_phase(const MathTables& T, cx<Re> kz, Re D) {
   return cexp_tab(T, mk(D * kz.im, -D * kz.re));
 }
 
-__device__ __forceinline__ Root medium_root(const Layers& L, double kz0sq, int m) {
-  return kz_root(kz_real_part(kz0sq, L.A(m)), -L.B(m));
+// kz of medium m: w = kz0^2 - A_m - i B_m, with kz0^2 - A_m formed in FP64.
+template <class P>
+__device__ __forceinline__ RootT<typename P::real> medium_root(const Layers<P>& L, double kz0sq,
+                                                               int m) {
+  using Re = typename P::real;
+  return kz_root(static_cast<Re>(kz_real_part(kz0sq, L.A(m))), -L.B(m));
+}
+
+template <class P>
+__device__ __forceinline__ cx<typename P::real> fronting_kz(double q) {
+  using Re = typename P::real;
+  return mk(static_cast<Re>(0.5 * q), Re(0));
 }
 
 // ---------------------------------------------------------------------------
 // Forward-only reflectivity of one node (no state kept; runtime layer loop).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double node_reflectivity(const MathTables& T, const Layers& L, int N,
+template <class P>
+__device__ __forceinline__ double node_reflectivity(const MathTables& T, const Layers<P>& L, int N,
                                                     double q) {
+  using Re = typename P::real;
+  using Cx = cx<Re>;
   const double kz0sq = kz0_squared(q);
-  cd kzn = medium_root(L, kz0sq, N + 1).kz;
-  cd P = mk(1.0, 0.0), Qv = mk(0.0, 0.0);
+  Cx kzn = medium_root(L, kz0sq, N + 1).kz;
+  Cx Pv = mk(Re(1), Re(0)), Qv = mk(Re(0), Re(0));
   for (int jj = N; jj >= 1; --jj) {
-    const cd kzc = medium_root(L, kz0sq, jj).kz;
-    const Iface it = interface_coeffs(T, kzc, kzn, L.Nr(jj), L.Ni(jj), L.C(jj));
-    const cd Pn = P + it.rp * Qv;
-    const cd t = it.rp * P + Qv;
+    const Cx kzc = medium_root(L, kz0sq, jj).kz;
+    const Iface<Re> it = interface_coeffs(T, kzc, kzn, L.Nr(jj), L.Ni(jj), L.C(jj));
+    const Cx Pn = Pv + it.rp * Qv;
+    const Cx t = it.rp * Pv + Qv;
     Qv = layer_phase(T, kzc, L.D(jj)) * t;
-    P = Pn;
+    Pv = Pn;
     kzn = kzc;
   }
   {
-    const Iface it = interface_coeffs(T, mk(0.5 * q, 0.0), kzn, L.Nr(0), L.Ni(0), L.C(0));
-    const cd Pn = P + it.rp * Qv;
-    Qv = it.rp * P + Qv;
-    P = Pn;
+    const Iface<Re> it = interface_coeffs(T, fronting_kz<P>(q), kzn, L.Nr(0), L.Ni(0), L.C(0));
+    const Cx Pn = Pv + it.rp * Qv;
+    Qv = it.rp * Pv + Qv;
+    Pv = Pn;
   }
-  return cabs2(Qv * crecip(P));
+  return (double)cabs2(Qv * crecip(Pv));
 }
 
 // Shared WU prologue.
@@ -223,6 +240,15 @@ __device__ __forceinline__ WuInfo tail_setup(const KernelArgs& a, int w, int lan
   return u;
 }
 
+template <class P>
+__device__ __forceinline__ Layers<P> item_layers(const KernelArgs& a, int64_t roff, int k) {
+  Layers<P> L;
+  L.rec = a.consts + roff * kRec;
+  L.recf = a.constsf + roff * kRecF;
+  L.z = k & a.zero_mask;
+  return L;
+}
+
 __device__ __forceinline__ void flag(int32_t* status, int item, uint32_t bits) {
   if (status != nullptr && bits != 0u)
     atomicOr(reinterpret_cast<unsigned int*>(status + item), bits);
@@ -231,13 +257,13 @@ __device__ __forceinline__ void flag(int32_t* status, int item, uint32_t bits) {
 // ---------------------------------------------------------------------------
 // R_hat per point (nr_reflectivity).
 // ---------------------------------------------------------------------------
+template <class P>
 __global__ __launch_bounds__(64) void k_reflectivity(KernelArgs a) {
   __shared__ Shared s;
   const int lane = threadIdx.x;
   const int w = blockIdx.x;
   const WuInfo u = wu_setup(a, w, lane);
   stage_shared(s, lane, a.rule);
-  const double* lrec = a.consts + u.roff * kRec;
   const int K = (u.dqq > 0.0) ? kSmearNodes : 1;
   double Rsm = 0.0;
   bool badq = !(u.Q > 0.0);
@@ -245,8 +271,7 @@ __global__ __launch_bounds__(64) void k_reflectivity(KernelArgs a) {
     const double q = (K == 1) ? u.Q : smear_node(u.Q, u.dqq, ld(s.t[k]));
     badq |= !(q > 0.0);
     const double wk = (K == 1) ? 1.0 : ld(s.w[k]);
-    const Layers L{lrec, k & a.zero_mask};
-    Rsm += wk * node_reflectivity(s.tab, L, u.N, q);
+    Rsm += wk * node_reflectivity(s.tab, item_layers<P>(a, u.roff, k), u.N, q);
   }
   if (u.active) {
     double Rhat = a.scale[u.item] * Rsm + a.bkg[u.item];
@@ -276,13 +301,13 @@ __device__ __forceinline__ double point_loglik(double Rhat, double Robs, double 
 // ---------------------------------------------------------------------------
 // logL partial per WU (nr_loglik): record = 1 double.
 // ---------------------------------------------------------------------------
+template <class P>
 __global__ __launch_bounds__(64) void k_loglik(KernelArgs a) {
   __shared__ Shared s;
   const int lane = threadIdx.x;
   const int w = blockIdx.x;
   const WuInfo u = wu_setup(a, w, lane);
   stage_shared(s, lane, a.rule);
-  const double* lrec = a.consts + u.roff * kRec;
   const int K = (u.dqq > 0.0) ? kSmearNodes : 1;
   double Rsm = 0.0;
   bool badq = !(u.Q > 0.0);
@@ -290,8 +315,7 @@ __global__ __launch_bounds__(64) void k_loglik(KernelArgs a) {
     const double q = (K == 1) ? u.Q : smear_node(u.Q, u.dqq, ld(s.t[k]));
     badq |= !(q > 0.0);
     const double wk = (K == 1) ? 1.0 : ld(s.w[k]);
-    const Layers L{lrec, k & a.zero_mask};
-    Rsm += wk * node_reflectivity(s.tab, L, u.N, q);
+    Rsm += wk * node_reflectivity(s.tab, item_layers<P>(a, u.roff, k), u.N, q);
   }
   double ll = 0.0;
   uint32_t bits = 0;
@@ -311,20 +335,23 @@ __global__ __launch_bounds__(64) void k_loglik(KernelArgs a) {
 // coefficients, the phase e_j (j >= 1).  Out: cotangents of the state entering
 // the level, kzbar contributions, and the d / sigma accumulators.
 // ---------------------------------------------------------------------------
+template <class Re>
 struct AdjStep {
-  cd Pb, Qb;   // cotangents of the state entering level j
-  cd kzb_c;    // contribution to kzbar_j
-  cd kzb_n;    // contribution to kzbar_{j+1}
-  double dd;   // dl/dd_j
-  double ss;   // Re(conj(ubar) kz_j kz_{j+1})  (times -4 sigma_{j+1} later)
+  cx<Re> Pb, Qb;   // cotangents of the state entering level j
+  cx<Re> kzb_c;    // contribution to kzbar_j
+  cx<Re> kzb_n;    // contribution to kzbar_{j+1}
+  Re dd;           // dl/dd_j
+  Re ss;           // Re(conj(ubar) kz_j kz_{j+1})  (times -4 sigma_{j+1} later)
 };
 
-__device__ __forceinline__ AdjStep adjoint_step(cd Ps, cd Qs, cd Pb, cd Qb, cd kzc, cd kzn,
-                                                const Iface& it, double C, bool has_phase, cd e,
-                                                double D) {
-  AdjStep o;
-  const cd t = it.rp * Ps + Qs;
-  cd tb, eb = mk(0.0, 0.0);
+template <class Re>
+__device__ __forceinline__ AdjStep<Re> adjoint_step(cx<Re> Ps, cx<Re> Qs, cx<Re> Pb, cx<Re> Qb,
+                                                    cx<Re> kzc, cx<Re> kzn, const Iface<Re>& it,
+                                                    Re C, bool has_phase, cx<Re> e, Re D) {
+  using Cx = cx<Re>;
+  AdjStep<Re> o;
+  const Cx t = it.rp * Ps + Qs;
+  Cx tb, eb = mk(Re(0), Re(0));
   if (has_phase) {
     eb = cmulc(t, Qb);
     tb = cmulc(e, Qb);
@@ -332,178 +359,200 @@ __device__ __forceinline__ AdjStep adjoint_step(cd Ps, cd Qs, cd Pb, cd Qb, cd k
     tb = Qb;
   }
   // P_new = P + r' Qv ; t = r' P + Qv
-  const cd rpb = cmulc(Qs, Pb) + cmulc(Ps, tb);
+  const Cx rpb = cmulc(Qs, Pb) + cmulc(Ps, tb);
   o.Pb = Pb + cmulc(it.rp, tb);
   o.Qb = cmulc(it.rp, Pb) + tb;
   // r' = r f, f = exp(C kz_j kz_{j+1})
-  const cd rb = cmulc(it.f, rpb);
-  const cd ub = cmulc(it.rp, rpb);
+  const Cx rb = cmulc(it.f, rpb);
+  const Cx ub = cmulc(it.rp, rpb);
   o.ss = ub.re * it.kk.re + ub.im * it.kk.im;
   // r = (kz_j - kz_{j+1}) s: dr/dkz_j = 2 kz_{j+1} s^2, dr/dkz_{j+1} = -2 kz_j s^2
-  const cd s2 = it.s * it.s;
-  o.kzb_c = cmulc(C * kzn, ub) + cmulc(2.0 * (kzn * s2), rb);
-  o.kzb_n = cmulc(C * kzc, ub) + cmulc(-2.0 * (kzc * s2), rb);
-  o.dd = 0.0;
+  const Cx s2 = it.s * it.s;
+  o.kzb_c = cmulc(C * kzn, ub) + cmulc(Re(2) * (kzn * s2), rb);
+  o.kzb_n = cmulc(C * kzc, ub) + cmulc(Re(-2) * (kzc * s2), rb);
+  o.dd = Re(0);
   if (has_phase) {
     // e = exp(-2 i kz d): de/dkz = -i D e, de/dd = -2 i kz e
     o.kzb_c += cmulc(mk(D * e.im, -D * e.re), eb);
-    const cd ze = kzc * e;
-    o.dd = eb.re * (2.0 * ze.im) + eb.im * (-2.0 * ze.re);
+    const Cx ze = kzc * e;
+    o.dd = eb.re * (Re(2) * ze.im) + eb.im * (Re(-2) * ze.re);
   }
   return o;
 }
 
 // wbar = conj(dkz/dw) kzbar = conj(1/(2 kz)) kzbar = kz kzbar / (2 |kz|^2)
-__device__ __forceinline__ cd wbar_of(cd kz, double inv_abs2, cd kzb) {
-  return (0.5 * inv_abs2) * (kz * kzb);
+template <class Re>
+__device__ __forceinline__ cx<Re> wbar_of(cx<Re> kz, Re inv_abs2, cx<Re> kzb) {
+  return (Re(0.5) * inv_abs2) * (kz * kzb);
 }
 
-// Per-lane gradient accumulators for one point: sum_k w_k dR(q_k)/d(.)
+// Per-lane gradient accumulators for one point, FP64 in both precisions:
+// sum_k w_k dR(q_k)/d(.)
 template <int LMAX>
 struct Accum {
   cd Hw[LMAX + 2];
   double Hd[LMAX + 2], Hs[LMAX + 2];
 };
 
-template <int LMAX>
-struct GradTape {
-  // per-lane state entering each level and the layer phase, lane-minor
-  double2 P[LMAX + 1][64], Qv[LMAX + 1][64], E[LMAX + 1][64];
+// LDS tape of the store variant: per-lane state entering each level and the
+// layer phase, lane-minor.
+template <class Re>
+struct TapeEntry;
+template <>
+struct TapeEntry<double> {
+  using type = double2;
+};
+template <>
+struct TapeEntry<float> {
+  using type = float2;
 };
 
-__device__ __forceinline__ double2 to_d2(cd z) { return make_double2(z.re, z.im); }
-__device__ __forceinline__ cd from_d2(double2 v) { return mk(v.x, v.y); }
+template <class Re, int LMAX>
+struct GradTape {
+  using V = typename TapeEntry<Re>::type;
+  V P[LMAX + 1][64], Qv[LMAX + 1][64], E[LMAX + 1][64];
+};
+
+__device__ __forceinline__ double2 to_v2(cd z) { return make_double2(z.re, z.im); }
+__device__ __forceinline__ float2 to_v2(cf z) { return make_float2(z.re, z.im); }
+__device__ __forceinline__ cd from_v2(double2 v) { return mk(v.x, v.y); }
+__device__ __forceinline__ cf from_v2(float2 v) { return mk(v.x, v.y); }
 
 // ---------------------------------------------------------------------------
 // One node, store variant: forward with the tape in LDS and kz in registers,
 // then the adjoint.  Returns R(q) and adds w_k dR/d(.) to the accumulators.
 // ---------------------------------------------------------------------------
-template <int LMAX>
-__device__ __forceinline__ double node_grad_store(const MathTables& T, const Layers& L,
-                                                  GradTape<LMAX>& tp, Accum<LMAX>& acc, int N,
-                                                  int lane, double q, double wk) {
+template <class P, int LMAX>
+__device__ __forceinline__ double node_grad_store(const MathTables& T, const Layers<P>& L,
+                                                  GradTape<typename P::real, LMAX>& tp,
+                                                  Accum<LMAX>& acc, int N, int lane, double q,
+                                                  double wk) {
+  using Re = typename P::real;
+  using Cx = cx<Re>;
   const double kz0sq = kz0_squared(q);
-  cd kz[LMAX + 2];
-  double ia[LMAX + 2];
-  Iface ifc[LMAX + 1];
-  cd P = mk(1.0, 0.0), Qv = mk(0.0, 0.0);
+  Cx kz[LMAX + 2];
+  Re ia[LMAX + 2];
+  Iface<Re> ifc[LMAX + 1];
+  Cx Pv = mk(Re(1), Re(0)), Qv = mk(Re(0), Re(0));
 #pragma unroll
   for (int jj = LMAX + 1; jj >= 0; --jj) {
     if (jj == N + 1) {
-      const Root rt = medium_root(L, kz0sq, jj);
+      const RootT<Re> rt = medium_root(L, kz0sq, jj);
       kz[jj] = rt.kz;
       ia[jj] = rt.inv_abs2;
     } else if (jj <= N) {
       if (jj == 0) {
-        kz[0] = mk(0.5 * q, 0.0);
-        ia[0] = 0.0;
+        kz[0] = fronting_kz<P>(q);
+        ia[0] = Re(0);
       } else {
-        const Root rt = medium_root(L, kz0sq, jj);
+        const RootT<Re> rt = medium_root(L, kz0sq, jj);
         kz[jj] = rt.kz;
         ia[jj] = rt.inv_abs2;
       }
-      const Iface it =
+      const Iface<Re> it =
           interface_coeffs(T, kz[jj], kz[jj + 1], L.Nr(jj), L.Ni(jj), L.C(jj));
       ifc[jj] = it;
-      tp.P[jj][lane] = to_d2(P);
-      tp.Qv[jj][lane] = to_d2(Qv);
-      const cd Pn = P + it.rp * Qv;
-      const cd t = it.rp * P + Qv;
+      tp.P[jj][lane] = to_v2(Pv);
+      tp.Qv[jj][lane] = to_v2(Qv);
+      const Cx Pn = Pv + it.rp * Qv;
+      const Cx t = it.rp * Pv + Qv;
       if (jj >= 1) {
-        const cd e = layer_phase(T, kz[jj], L.D(jj));
-        tp.E[jj][lane] = to_d2(e);
+        const Cx e = layer_phase(T, kz[jj], L.D(jj));
+        tp.E[jj][lane] = to_v2(e);
         Qv = e * t;
       } else {
         Qv = t;
       }
-      P = Pn;
+      Pv = Pn;
     }
   }
-  const cd iP = crecip(P);
-  const cd r = Qv * iP;
-  const cd rbar = (2.0 * wk) * r;
-  cd Pb = cmulc(-(r * iP), rbar);  // conj(dr/dP) rbar, dr/dP = -r/P
-  cd Qb = cmulc(iP, rbar);         // conj(dr/dQv) rbar, dr/dQv = 1/P
-  cd kzbc = mk(0.0, 0.0);
+  const Cx iP = crecip(Pv);
+  const Cx r = Qv * iP;
+  const Cx rbar = static_cast<Re>(2.0 * wk) * r;
+  Cx Pb = cmulc(-(r * iP), rbar);  // conj(dr/dP) rbar, dr/dP = -r/P
+  Cx Qb = cmulc(iP, rbar);         // conj(dr/dQv) rbar, dr/dQv = 1/P
+  Cx kzbc = mk(Re(0), Re(0));
 #pragma unroll
   for (int jj = 0; jj <= LMAX; ++jj) {
     if (jj <= N) {
-      const double C = L.C(jj);
-      const Iface& it = ifc[jj];
-      const cd Ps = from_d2(tp.P[jj][lane]);
-      const cd Qs = from_d2(tp.Qv[jj][lane]);
+      const Re C = L.C(jj);
+      const Iface<Re>& it = ifc[jj];
+      const Cx Ps = from_v2(tp.P[jj][lane]);
+      const Cx Qs = from_v2(tp.Qv[jj][lane]);
       const bool ph = jj >= 1;
-      const cd e = ph ? from_d2(tp.E[jj][lane]) : mk(1.0, 0.0);
-      const AdjStep st =
-          adjoint_step(Ps, Qs, Pb, Qb, kz[jj], kz[jj + 1], it, C, ph, e, ph ? L.D(jj) : 0.0);
+      const Cx e = ph ? from_v2(tp.E[jj][lane]) : mk(Re(1), Re(0));
+      const AdjStep<Re> st =
+          adjoint_step(Ps, Qs, Pb, Qb, kz[jj], kz[jj + 1], it, C, ph, e, ph ? L.D(jj) : Re(0));
       kzbc += st.kzb_c;
-      acc.Hs[jj + 1] += st.ss;
+      acc.Hs[jj + 1] += (double)st.ss;
       if (ph) {
-        acc.Hd[jj] += st.dd;
-        acc.Hw[jj] += wbar_of(kz[jj], ia[jj], kzbc);
+        acc.Hd[jj] += (double)st.dd;
+        acc.Hw[jj] += widen(wbar_of(kz[jj], ia[jj], kzbc));
       }
-      if (jj == N) acc.Hw[jj + 1] += wbar_of(kz[jj + 1], ia[jj + 1], st.kzb_n);
+      if (jj == N) acc.Hw[jj + 1] += widen(wbar_of(kz[jj + 1], ia[jj + 1], st.kzb_n));
       Pb = st.Pb;
       Qb = st.Qb;
       kzbc = st.kzb_n;
     }
   }
-  return cabs2(r);
+  return (double)cabs2(r);
 }
 
 // ---------------------------------------------------------------------------
 // One node, recompute variant: the state tape stays in registers; the adjoint
 // recomputes each medium's wavevector and each layer's phase.
 // ---------------------------------------------------------------------------
-template <int LMAX>
-__device__ __forceinline__ double node_grad_recompute(const MathTables& T, const Layers& L,
+template <class P, int LMAX>
+__device__ __forceinline__ double node_grad_recompute(const MathTables& T, const Layers<P>& L,
                                                       Accum<LMAX>& acc, int N, double q,
                                                       double wk) {
+  using Re = typename P::real;
+  using Cx = cx<Re>;
   const double kz0sq = kz0_squared(q);
-  const cd kz0 = mk(0.5 * q, 0.0);
-  cd tapeP[LMAX + 1], tapeQ[LMAX + 1];
-  cd kzn = medium_root(L, kz0sq, N + 1).kz;
-  cd P = mk(1.0, 0.0), Qv = mk(0.0, 0.0);
+  const Cx kz0 = fronting_kz<P>(q);
+  Cx tapeP[LMAX + 1], tapeQ[LMAX + 1];
+  Cx kzn = medium_root(L, kz0sq, N + 1).kz;
+  Cx Pv = mk(Re(1), Re(0)), Qv = mk(Re(0), Re(0));
 #pragma unroll
   for (int jj = LMAX; jj >= 0; --jj) {
     if (jj <= N) {
-      const cd kzc = (jj == 0) ? kz0 : medium_root(L, kz0sq, jj).kz;
-      tapeP[jj] = P;
+      const Cx kzc = (jj == 0) ? kz0 : medium_root(L, kz0sq, jj).kz;
+      tapeP[jj] = Pv;
       tapeQ[jj] = Qv;
-      const Iface it = interface_coeffs(T, kzc, kzn, L.Nr(jj), L.Ni(jj), L.C(jj));
-      const cd Pn = P + it.rp * Qv;
-      const cd t = it.rp * P + Qv;
+      const Iface<Re> it = interface_coeffs(T, kzc, kzn, L.Nr(jj), L.Ni(jj), L.C(jj));
+      const Cx Pn = Pv + it.rp * Qv;
+      const Cx t = it.rp * Pv + Qv;
       Qv = (jj >= 1) ? layer_phase(T, kzc, L.D(jj)) * t : t;
-      P = Pn;
+      Pv = Pn;
       kzn = kzc;
     }
     __builtin_amdgcn_sched_barrier(0x0100);  // only LDS reads may move across
   }
-  const cd iP = crecip(P);
-  const cd r = Qv * iP;
-  const cd rbar = (2.0 * wk) * r;
-  cd Pb = cmulc(-(r * iP), rbar);
-  cd Qb = cmulc(iP, rbar);
-  cd kzc = kz0;
-  double iac = 0.0;
-  cd kzbc = mk(0.0, 0.0);
+  const Cx iP = crecip(Pv);
+  const Cx r = Qv * iP;
+  const Cx rbar = static_cast<Re>(2.0 * wk) * r;
+  Cx Pb = cmulc(-(r * iP), rbar);
+  Cx Qb = cmulc(iP, rbar);
+  Cx kzc = kz0;
+  Re iac = Re(0);
+  Cx kzbc = mk(Re(0), Re(0));
 #pragma unroll
   for (int jj = 0; jj <= LMAX; ++jj) {
     if (jj <= N) {
-      const Root rn = medium_root(L, kz0sq, jj + 1);
-      const double C = L.C(jj);
-      const Iface it = interface_coeffs(T, kzc, rn.kz, L.Nr(jj), L.Ni(jj), C);
+      const RootT<Re> rn = medium_root(L, kz0sq, jj + 1);
+      const Re C = L.C(jj);
+      const Iface<Re> it = interface_coeffs(T, kzc, rn.kz, L.Nr(jj), L.Ni(jj), C);
       const bool ph = jj >= 1;
-      const double D = ph ? L.D(jj) : 0.0;
-      const cd e = ph ? layer_phase(T, kzc, D) : mk(1.0, 0.0);
-      const AdjStep st = adjoint_step(tapeP[jj], tapeQ[jj], Pb, Qb, kzc, rn.kz, it, C, ph, e, D);
+      const Re D = ph ? L.D(jj) : Re(0);
+      const Cx e = ph ? layer_phase(T, kzc, D) : mk(Re(1), Re(0));
+      const AdjStep<Re> st = adjoint_step(tapeP[jj], tapeQ[jj], Pb, Qb, kzc, rn.kz, it, C, ph, e, D);
       kzbc += st.kzb_c;
-      acc.Hs[jj + 1] += st.ss;
+      acc.Hs[jj + 1] += (double)st.ss;
       if (ph) {
-        acc.Hd[jj] += st.dd;
-        acc.Hw[jj] += wbar_of(kzc, iac, kzbc);
+        acc.Hd[jj] += (double)st.dd;
+        acc.Hw[jj] += widen(wbar_of(kzc, iac, kzbc));
       }
-      if (jj == N) acc.Hw[jj + 1] += wbar_of(rn.kz, rn.inv_abs2, st.kzb_n);
+      if (jj == N) acc.Hw[jj + 1] += widen(wbar_of(rn.kz, rn.inv_abs2, st.kzb_n));
       Pb = st.Pb;
       Qb = st.Qb;
       kzc = rn.kz;
@@ -512,7 +561,7 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
     }
     __builtin_amdgcn_sched_barrier(0x0100);  // only LDS reads may move across
   }
-  return cabs2(r);
+  return (double)cabs2(r);
 }
 
 // ---------------------------------------------------------------------------
@@ -524,16 +573,16 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
 //   [3 + 2NR + m]  sum dl/dd_m
 //   [3 + 3NR + m]  sum Re(conj(ubar) kz_{m-1} kz_m)   (sigma_m factor applied later)
 // ---------------------------------------------------------------------------
-template <int LMAX, bool STORE, bool TAIL>
+template <class P, int LMAX, bool STORE, bool TAIL>
 __global__ __launch_bounds__(64) void k_loglik_grad(KernelArgs a) {
+  using Re = typename P::real;
   __shared__ Shared s;
-  using Tape = typename std::conditional<STORE, GradTape<LMAX>, char>::type;
+  using Tape = typename std::conditional<STORE, GradTape<Re, LMAX>, char>::type;
   __shared__ Tape tape;
   const int lane = threadIdx.x;
   const int w = blockIdx.x;
   const WuInfo u = TAIL ? tail_setup(a, w, lane) : wu_setup(a, w, lane);
   stage_shared(s, lane, a.rule);
-  const double* lrec = a.consts + u.roff * kRec;
   const int N = u.N;
   const int K = (u.dqq > 0.0) ? kSmearNodes : 1;
 
@@ -551,12 +600,12 @@ __global__ __launch_bounds__(64) void k_loglik_grad(KernelArgs a) {
     const double q = (K == 1) ? u.Q : smear_node(u.Q, u.dqq, ld(s.t[k]));
     badq |= !(q > 0.0);
     const double wk = (K == 1) ? 1.0 : ld(s.w[k]);
-    const Layers L{lrec, k & a.zero_mask};
+    const Layers<P> L = item_layers<P>(a, u.roff, k);
     double R;
     if constexpr (STORE)
-      R = node_grad_store<LMAX>(s.tab, L, tape, acc, N, lane, q, wk);
+      R = node_grad_store<P, LMAX>(s.tab, L, tape, acc, N, lane, q, wk);
     else
-      R = node_grad_recompute<LMAX>(s.tab, L, acc, N, q, wk);
+      R = node_grad_recompute<P, LMAX>(s.tab, L, acc, N, q, wk);
     Rsm += wk * R;
   }
 
@@ -647,94 +696,30 @@ __global__ __launch_bounds__(64) void k_loglik_grad(KernelArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Deterministic per-item reductions of the WU records.
+// Launchers of one precision (instantiated in nr_kernels_f64.hip and
+// nr_kernels_f32.hip).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_reduce_loglik(ReduceArgs a) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= a.n_items) return;
-  const int64_t first = a.item_wu_first[b];
-  const int cnt = a.item_wu_count[b];
-  double s = 0.0;
-  for (int k = 0; k < cnt; ++k) s += a.rec[a.rec_of_wu[first + k]];
-  a.logL[b] = s;
-}
-
-// One wave per item: lanes sum record fields over the item's WUs, then turn
-// the sums into gradients of the row entries.
-__global__ __launch_bounds__(64) void k_reduce_grad(ReduceArgs a) {
-  extern __shared__ double fsum[];
-  const int b = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int64_t first = a.item_wu_first[b];
-  const int cnt = a.item_wu_count[b];
-  const int64_t roff = a.row_off[b];
-  const int NR = (int)(a.row_off[b + 1] - roff);
-  const int nf = 3 + 4 * NR;
-  for (int f = lane; f < nf; f += 64) {
-    double v = 0.0;
-    for (int k = 0; k < cnt; ++k) v += a.rec[a.rec_of_wu[first + k] + f];
-    fsum[f] = v;
-  }
-  __syncthreads();
-  const double* rows = a.layers + 4 * roff;
-  double* g = a.g_rows + 4 * roff;
-  for (int m = lane; m < NR; m += 64) {
-    const double wr = fsum[3 + m], wi = fsum[3 + NR + m];
-    const double dd = fsum[3 + 2 * NR + m], ss = fsum[3 + 3 * NR + m];
-    double gd = 0.0, gre = 0.0, gim = 0.0, gsig = 0.0;
-    if (m >= 1) {
-      gre = -kFourPi * wr;
-      const double sgn = (rows[4 * m + 2] < 0.0) ? -1.0 : 1.0;
-      gim = -kFourPi * sgn * wi;
-      gsig = -4.0 * rows[4 * m + 3] * ss;
-      if (m <= NR - 2) gd = dd;
-    }
-    g[4 * m + 0] = gd;
-    g[4 * m + 1] = gre;
-    g[4 * m + 2] = gim;
-    g[4 * m + 3] = gsig;
-  }
-  // fronting rho_re: the model depends on rho_re,m - rho_re,0 only
-  double part = 0.0;
-  for (int m = 1 + lane; m < NR; m += 64) part += fsum[3 + m];
-  part = wave_sum(part);
-  if (lane == 0) {
-    g[1] = kFourPi * part;
-    a.logL[b] = fsum[0];
-    a.g_inst[2 * b + 0] = fsum[1];
-    a.g_inst[2 * b + 1] = fsum[2];
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Launchers
-// ---------------------------------------------------------------------------
-hipError_t launch_item_consts(const int64_t* row_off, const double* layers, double* rec,
-                              int n_items, hipStream_t st) {
-  if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_item_consts, dim3(n_items), dim3(64), 0, st, row_off, layers, rec, n_items);
-  return hipGetLastError();
-}
-
-hipError_t launch_forward(int op, const KernelArgs& a, int n_wu, hipStream_t st) {
+template <class P>
+hipError_t launch_forward_p(int op, const KernelArgs& a, int n_wu, hipStream_t st) {
   if (n_wu <= 0) return hipSuccess;
   if (op == kOpReflectivity)
-    hipLaunchKernelGGL(k_reflectivity, dim3(n_wu), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_reflectivity<P>, dim3(n_wu), dim3(64), 0, st, a);
   else
-    hipLaunchKernelGGL(k_loglik, dim3(n_wu), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_loglik<P>, dim3(n_wu), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_grad(int bucket, bool tail, const KernelArgs& a, int n_wu, hipStream_t st) {
+template <class P>
+hipError_t launch_grad_p(int bucket, bool tail, const KernelArgs& a, int n_wu, hipStream_t st) {
   if (n_wu <= 0) return hipSuccess;
   switch (kBucketLmax[bucket]) {
 #define NR_CASE(LM)                                                                           \
   case LM:                                                                                    \
     if (tail)                                                                                 \
-      hipLaunchKernelGGL((k_loglik_grad<LM, (LM <= kStoreMaxLayers), true>), dim3(n_wu),      \
+      hipLaunchKernelGGL((k_loglik_grad<P, LM, (LM <= P::kStoreMax), true>), dim3(n_wu),      \
                          dim3(64), 0, st, a);                                                 \
     else                                                                                      \
-      hipLaunchKernelGGL((k_loglik_grad<LM, (LM <= kStoreMaxLayers), false>), dim3(n_wu),     \
+      hipLaunchKernelGGL((k_loglik_grad<P, LM, (LM <= P::kStoreMax), false>), dim3(n_wu),     \
                          dim3(64), 0, st, a);                                                 \
     return hipGetLastError();
     NR_BUCKETS(NR_CASE)
@@ -742,17 +727,6 @@ hipError_t launch_grad(int bucket, bool tail, const KernelArgs& a, int n_wu, hip
     default:
       return hipErrorInvalidValue;
   }
-}
-
-hipError_t launch_reduce(int op, const ReduceArgs& a, hipStream_t st) {
-  if (a.n_items <= 0) return hipSuccess;
-  if (op == kOpLoglik) {
-    hipLaunchKernelGGL(k_reduce_loglik, dim3((a.n_items + 255) / 256), dim3(256), 0, st, a);
-  } else {
-    const size_t shmem = sizeof(double) * (3 + 4 * (kMaxLayers + 2));
-    hipLaunchKernelGGL(k_reduce_grad, dim3(a.n_items), dim3(64), shmem, st, a);
-  }
-  return hipGetLastError();
 }
 
 }  // namespace nr

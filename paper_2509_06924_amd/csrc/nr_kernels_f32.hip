@@ -1,0 +1,15 @@
+// FP32 instantiation of the kernels (layer product and adjoint in float;
+// kz0^2 - 4 pi drho, smearing, chi^2 and gradient accumulation in FP64).
+#include "nr_kernels.hpp"
+
+namespace nr {
+
+hipError_t launch_forward_f32(int op, const KernelArgs& a, int n_wu, hipStream_t st) {
+  return launch_forward_p<F32>(op, a, n_wu, st);
+}
+
+hipError_t launch_grad_f32(int bucket, bool tail, const KernelArgs& a, int n_wu, hipStream_t st) {
+  return launch_grad_p<F32>(bucket, tail, a, n_wu, st);
+}
+
+}  // namespace nr

@@ -1,0 +1,136 @@
+// FP64 instantiation of the kernels, the per-item constant prologue, the
+// per-item reductions, and the launch entry points of both precisions.
+#include "nr_kernels.hpp"
+
+namespace nr {
+
+// One block of 64 per item, one lane per medium: the item's layer records
+// (doubles and their float copies for the FP32 variant).
+__global__ __launch_bounds__(64) void k_item_consts(const int64_t* row_off, const double* layers,
+                                                    double* rec, float* recf, int n_items) {
+  const int b = blockIdx.x;
+  const int m = threadIdx.x;
+  if (b >= n_items) return;
+  const int64_t r0 = row_off[b];
+  const int NR = (int)(row_off[b + 1] - r0);
+  if (m >= NR) return;
+  const double* rows = layers + 4 * r0;
+  const double rho0 = rows[1];
+  auto Af = [&](int j) { return (j == 0) ? 0.0 : kFourPi * (rows[4 * j + 1] - rho0); };
+  auto Bf = [&](int j) { return (j == 0) ? 0.0 : kFourPi * fabs(rows[4 * j + 2]); };
+  double v[kRecDoubles];
+  const double A = Af(m), B = Bf(m);
+  v[0] = A;
+  v[1] = B;
+  if (m + 1 < NR) {
+    const double sg = rows[4 * (m + 1) + 3];
+    v[2] = Af(m + 1) - A;
+    v[3] = Bf(m + 1) - B;
+    v[4] = -2.0 * (sg * sg);
+  } else {
+    v[2] = 0.0;
+    v[3] = 0.0;
+    v[4] = 0.0;
+  }
+  v[5] = 2.0 * rows[4 * m];
+  double* out = rec + (r0 + m) * kRecDoubles;
+  for (int f = 0; f < kRecDoubles; ++f) out[f] = v[f];
+  float* outf = recf + (r0 + m) * kRecFloats;
+  for (int f = 0; f < 5; ++f) outf[f] = (float)v[f + 1];
+  for (int f = 5; f < kRecFloats; ++f) outf[f] = 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic per-item reductions of the WU records.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_reduce_loglik(ReduceArgs a) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.n_items) return;
+  const int64_t first = a.item_wu_first[b];
+  const int cnt = a.item_wu_count[b];
+  double s = 0.0;
+  for (int k = 0; k < cnt; ++k) s += a.rec[a.rec_of_wu[first + k]];
+  a.logL[b] = s;
+}
+
+// One wave per item: lanes sum record fields over the item's WUs, then turn
+// the sums into gradients of the row entries.
+__global__ __launch_bounds__(64) void k_reduce_grad(ReduceArgs a) {
+  extern __shared__ double fsum[];
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t first = a.item_wu_first[b];
+  const int cnt = a.item_wu_count[b];
+  const int64_t roff = a.row_off[b];
+  const int NR = (int)(a.row_off[b + 1] - roff);
+  const int nf = 3 + 4 * NR;
+  for (int f = lane; f < nf; f += 64) {
+    double v = 0.0;
+    for (int k = 0; k < cnt; ++k) v += a.rec[a.rec_of_wu[first + k] + f];
+    fsum[f] = v;
+  }
+  __syncthreads();
+  const double* rows = a.layers + 4 * roff;
+  double* g = a.g_rows + 4 * roff;
+  for (int m = lane; m < NR; m += 64) {
+    const double wr = fsum[3 + m], wi = fsum[3 + NR + m];
+    const double dd = fsum[3 + 2 * NR + m], ss = fsum[3 + 3 * NR + m];
+    double gd = 0.0, gre = 0.0, gim = 0.0, gsig = 0.0;
+    if (m >= 1) {
+      gre = -kFourPi * wr;
+      const double sgn = (rows[4 * m + 2] < 0.0) ? -1.0 : 1.0;
+      gim = -kFourPi * sgn * wi;
+      gsig = -4.0 * rows[4 * m + 3] * ss;
+      if (m <= NR - 2) gd = dd;
+    }
+    g[4 * m + 0] = gd;
+    g[4 * m + 1] = gre;
+    g[4 * m + 2] = gim;
+    g[4 * m + 3] = gsig;
+  }
+  // fronting rho_re: the model depends on rho_re,m - rho_re,0 only
+  double part = 0.0;
+  for (int m = 1 + lane; m < NR; m += 64) part += fsum[3 + m];
+  part = wave_sum(part);
+  if (lane == 0) {
+    g[1] = kFourPi * part;
+    a.logL[b] = fsum[0];
+    a.g_inst[2 * b + 0] = fsum[1];
+    a.g_inst[2 * b + 1] = fsum[2];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_item_consts(const int64_t* row_off, const double* layers, double* rec,
+                              float* recf, int n_items, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_item_consts, dim3(n_items), dim3(64), 0, st, row_off, layers, rec, recf,
+                     n_items);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(int precision, int op, const KernelArgs& a, int n_wu, hipStream_t st) {
+  return precision == NR_F32 ? launch_forward_f32(op, a, n_wu, st)
+                             : launch_forward_p<F64>(op, a, n_wu, st);
+}
+
+hipError_t launch_grad(int precision, int bucket, bool tail, const KernelArgs& a, int n_wu,
+                       hipStream_t st) {
+  return precision == NR_F32 ? launch_grad_f32(bucket, tail, a, n_wu, st)
+                             : launch_grad_p<F64>(bucket, tail, a, n_wu, st);
+}
+
+hipError_t launch_reduce(int op, const ReduceArgs& a, hipStream_t st) {
+  if (a.n_items <= 0) return hipSuccess;
+  if (op == kOpLoglik) {
+    hipLaunchKernelGGL(k_reduce_loglik, dim3((a.n_items + 255) / 256), dim3(256), 0, st, a);
+  } else {
+    const size_t shmem = sizeof(double) * (3 + 4 * (kMaxLayers + 2));
+    hipLaunchKernelGGL(k_reduce_grad, dim3(a.n_items), dim3(64), shmem, st, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace nr
