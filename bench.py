@@ -155,6 +155,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra-rows", action="store_true",
                     help="skip the forward-only and per-item (unbatched) rows")
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="skip the single-film, co-fit, ragged-HMC and VI rows")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=float, default=0.0,
                     help="only run a plain device copy of this size (counter calibration)")
@@ -253,6 +255,8 @@ def main():
         rec["forward_only"] = forward_only_row(prob, batch, args.steps)
         rec["plain_unbatched"] = plain_unbatched_row(nr, batch)
         rec["fp32"] = fp32_row(nr, batch, out, args.steps, hip)
+    if not args.no_extra_rows and args.workload == "c2" and not args.no_other_workloads:
+        rec["other_workloads"] = other_workloads(nr)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
     print(json.dumps(rec), flush=True)
@@ -323,6 +327,157 @@ def fp32_row(nr, batch, out64, steps, hip):
                     "kz0^2 - 4 pi drho, smearing, chi^2 and accumulation in FP64); errors "
                     "against the FP64 path over every item, gradient in natural units "
                     "relative to each item's largest component"}
+
+
+NATURAL_UNITS = (1.0, 1e-6, 1e-6, 1.0)  # d, rho_re, rho_im, sigma
+
+
+def _timed(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def single_film_row(nr):
+    """One draw of the 1-layer film, 200 points, unsmeared: latency of one
+    logL + gradient call (back to back; with a host sync per call; and as a
+    replayed graph)."""
+    import torch
+
+    from paper_2509_06924_amd import inputs
+    batch = inputs.c1_single_film()
+    prob = nr.Problem.from_batch(batch, device="cuda:0")
+    out = prob.loglik_grad()
+    stream = torch.cuda.current_stream()
+    back = _timed(lambda: prob.loglik_grad(out=out, stream=stream), 500)
+
+    def synced():
+        prob.loglik_grad(out=out, stream=stream)
+        torch.cuda.synchronize()
+    sync = _timed(synced, 200)
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        prob.loglik_grad(out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        prob.loglik_grad(out=out)
+    graph = _timed(g.replay, 500)
+    return {"what": "1 draw x 1-layer film x 200 Q, unsmeared, logL + gradient",
+            "us_per_call_back_to_back": back * 1e6, "us_per_call_synced": sync * 1e6,
+            "us_per_call_graph_replay": graph * 1e6,
+            "layer_steps_per_call": batch.layer_steps()}
+
+
+def cofit_row(nr, reps=10):
+    """1024 draws x 3 contrasts x 12 layers: logL + gradient per item, then the
+    tie-sum of the per-contrast gradients onto the 50 shared parameters."""
+    import numpy as np
+    import torch
+
+    from paper_2509_06924_amd import inputs
+    batch = inputs.c3_cofit()
+    prob = nr.Problem.from_batch(batch, device="cuda:0")
+    rows = int(batch.row_off[1] - batch.row_off[0])
+    per_draw = rows * 4  # all row entries but the backing rho_re, plus the shared bkg
+    nre = batch.layers.size
+    tie = -np.ones(nre + 2 * batch.n_items, np.int64)
+    for b in range(batch.n_items):
+        d = b // 3
+        k = 0
+        for r in range(rows):
+            for f in range(4):
+                if r == rows - 1 and f == 1:
+                    continue
+                tie[(batch.row_off[b] + r) * 4 + f] = d * per_draw + k
+                k += 1
+        tie[nre + 2 * b + 1] = d * per_draw + k
+    first, src = nr.tie_map_to_csr(tie, (batch.n_items // 3) * per_draw)
+    first_t = torch.as_tensor(first, device="cuda:0")
+    src_t = torch.as_tensor(src, device="cuda:0")
+    out = prob.loglik_grad()
+    stream = torch.cuda.current_stream()
+
+    def step():
+        prob.loglik_grad(out=out, stream=stream)
+        nr.tie_sum(first_t, src_t, torch.cat([out[1].reshape(-1), out[2].reshape(-1)]))
+    dt = _timed(step, reps)
+    return {"what": "1024 draws x 3 contrasts x 12 layers, Q 250/300/350, 5% dQ/Q: "
+                    "logL + gradient + tie-sum onto the shared parameters",
+            "ms_per_step": dt * 1e3, "value": batch.layer_steps() / dt, "unit": UNIT,
+            "shared_params_per_draw": per_draw}
+
+
+def ragged_hmc_row(nr, precision, n_steps=10):
+    """16384 ragged items (L 2..40, nQ 100..1000, dQ/Q 2-8%): n leapfrog steps
+    (half kick, drift, logL + gradient, half kick) captured in one HIP graph,
+    dt = 1e-3 in natural units (inverse mass = unit^2)."""
+    import numpy as np
+
+    from paper_2509_06924_amd import inputs
+    batch = inputs.c4_ragged()
+    prob = nr.Problem.from_batch(batch, device="cuda:0", precision=precision)
+    rng = np.random.default_rng(7)
+    units = np.array(NATURAL_UNITS)
+    mom_rows = rng.standard_normal(batch.layers.shape) / units
+    mom_inst = rng.standard_normal((batch.n_items, 2)) / np.array([1.0, 1e-7])
+    im_rows = np.tile(units ** 2, (batch.layers.shape[0], 1))
+    im_inst = np.tile(np.array([1.0, 1e-14]), (batch.n_items, 1))
+    st = nr.HmcState(prob, mom_rows, mom_inst, im_rows, im_inst)
+    graph = nr.LeapfrogGraph(prob, st, 1e-3, n_steps)
+    dt = _timed(graph.launch, 3) / n_steps
+    graph.close()
+    return {"what": "16384 ragged items, L 2..40, nQ 100..1000, dQ/Q 2-8%: HIP-graph leapfrog "
+                    f"({n_steps} steps per graph)",
+            "dtype": "f32" if precision == nr.NR_F32 else "f64",
+            "ms_per_leapfrog_step": dt * 1e3, "value": batch.layer_steps() / dt, "unit": UNIT,
+            "frac_fp64_peak": FLOP_PER_LAYER_STEP * batch.layer_steps() / dt / FP64_VALU_PEAK,
+            "layer_steps_per_step": batch.layer_steps()}
+
+
+def vi_row(nr, reps=5):
+    """8192 mean-field VI samples x 20 layers x 1000 Q, 5% dQ/Q: sampler,
+    logL + gradient per sample, and the ELBO gradient reduction."""
+    import numpy as np
+
+    from paper_2509_06924_amd import inputs
+    batch = inputs.c5_vi()
+    mu_rows = batch.meta["mu"]
+    L = mu_rows.shape[0] - 2
+    P = mu_rows.size + 2
+    mu = np.concatenate([mu_rows.reshape(-1), [1.0, 1e-7]])
+    mask = np.zeros(P, np.uint8)
+    mask[4:4 * (mu_rows.shape[0] - 1)] = 1  # the finite layers' 4 entries
+    mask[-2:] = 1
+    width = np.maximum(batch.meta["rel_width"] * np.abs(mu), 1e-12)
+    omega = np.log(np.expm1(width))
+    eps = np.random.default_rng(11).standard_normal((batch.n_items, P))
+    import torch
+    dev = dict(device="cuda:0")
+    mu, omega, eps = (torch.as_tensor(x, dtype=torch.float64, **dev) for x in (mu, omega, eps))
+    mask = torch.as_tensor(mask, **dev)
+    out = {}
+    for prec in (nr.NR_F64, nr.NR_F32):
+        prob = nr.Problem.from_batch(batch, device="cuda:0", precision=prec)
+        dt = _timed(lambda: prob.vi_elbo_grad(mu, omega, mask, eps), reps)
+        out["f32" if prec == nr.NR_F32 else "f64"] = {
+            "ms_per_step": dt * 1e3, "value": batch.layer_steps() / dt, "unit": UNIT}
+    out["what"] = (f"8192 samples x {L} layers x 1000 Q, 5% dQ/Q: sampler + logL + gradient + "
+                   "ELBO gradient, inputs resident on the device")
+    return out
+
+
+def other_workloads(nr):
+    return {"single_film": single_film_row(nr), "cofit": cofit_row(nr),
+            "ragged_hmc_f64": ragged_hmc_row(nr, nr.NR_F64),
+            "ragged_hmc_f32": ragged_hmc_row(nr, nr.NR_F32), "vi": vi_row(nr)}
 
 
 def plain_unbatched_row(nr, batch, n_items=64):
