@@ -76,12 +76,12 @@ void smearing_rule(double* t, double* w) {
 }
 
 // Tables for the device exp and sincos, correctly rounded from long double:
-// (sin, cos)(k pi/32) for k = 0..63, interleaved, then 2^(j/64) for j = 0..63.
+// (sin, cos)(k pi/64) for k = 0..127, interleaved, then 2^(j/64) for j = 0..63.
 void append_math_tables(std::vector<double>& v) {
   const long double pi = 3.141592653589793238462643383279502884L;
-  for (int k = 0; k < 64; ++k) {
-    v.push_back((double)std::sin(pi * k / 32.0L));
-    v.push_back((double)std::cos(pi * k / 32.0L));
+  for (int k = 0; k < 128; ++k) {
+    v.push_back((double)std::sin(pi * k / 64.0L));
+    v.push_back((double)std::cos(pi * k / 64.0L));
   }
   for (int j = 0; j < 64; ++j) v.push_back((double)std::exp2((long double)j / 64.0L));
 }

@@ -58,13 +58,12 @@ __device__ __forceinline__ T cabs2(cx<T> a) { return a.re * a.re + a.im * a.im; 
 __device__ __forceinline__ cd widen(cd a) { return a; }
 __device__ __forceinline__ cd widen(cf a) { return mk((double)a.re, (double)a.im); }
 
-// 1/x from the hardware estimate v_rcp_f64 refined by two Newton steps
-// r <- r + r (1 - x r); each step squares the relative error.
+// 1/x from the hardware estimate v_rcp_f64 (relative error about 2^-24,
+// measured on gfx950) refined by one Newton step r <- r + r (1 - x r), which
+// squares the error: about 2^-48 relative.
 __device__ __forceinline__ double rcp(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);
   return fma(r, e, r);
 }
 
@@ -74,26 +73,24 @@ __device__ __forceinline__ cd crecip(cd z) {
 }
 
 // 1/sqrt(a) from the hardware estimate v_rsq_f64 (about 2^-24 relative)
-// refined by two Newton steps y <- y + y/2 (1 - a y^2).
+// refined by one Newton step y <- y + y/2 (1 - a y^2): about 2^-47 relative.
 __device__ __forceinline__ double rsq(double a) {
-  double y = __builtin_amdgcn_rsq(a);
-  double e = fma(-(a * y), y, 1.0);
-  y = fma(0.5 * y, e, y);
-  e = fma(-(a * y), y, 1.0);
+  const double y = __builtin_amdgcn_rsq(a);
+  const double e = fma(-(a * y), y, 1.0);
   return fma(0.5 * y, e, y);
 }
 
 // ---------------------------------------------------------------------------
 // Table-driven exp and sincos.  The tables live in LDS, filled per block from
 // plan-owned device memory computed on the host in long double:
-//   sc[k] = (sin(k pi/32), cos(k pi/32)), k = 0..63
-//   e2[j] = 2^(j/64),                       j = 0..63
+//   sc[k] = (sin(k pi/64), cos(k pi/64)), k = 0..127
+//   e2[j] = 2^(j/64),                     j = 0..63
 // ---------------------------------------------------------------------------
 struct MathTables {
-  double sc[64][2];
+  double sc[128][2];
   double e2[64];
 };
-constexpr int kTableDoubles = 64 * 2 + 64;
+constexpr int kTableDoubles = 128 * 2 + 64;
 
 typedef __attribute__((address_space(3))) const double lds_double;
 
@@ -106,32 +103,30 @@ __device__ __forceinline__ int low_word(double t) {
   return (int)(unsigned int)__double_as_longlong(t);
 }
 
-// sin and cos of x: x = k pi/32 + r with pi/32 split in three doubles (FMA
-// Cody-Waite, |r| <= pi/64, accurate for |x| < 2^40), Taylor polynomials of
-// sin r to r^9 and cos r to r^8 (truncation < 1e-19 on |r| <= pi/64), then
-// the angle-addition formulas with the tabulated sin/cos of (k mod 64) pi/32.
+// sin and cos of x: x = k pi/64 + r with pi/64 split in two doubles (FMA
+// Cody-Waite; the dropped third part, 4.7e-35, times k is far below the
+// rounding of r for |x| < 1e12), |r| <= pi/128; Taylor polynomials of sin r
+// to r^7 and cos r to r^6 (truncation below 1e-20 and 3.3e-18 on
+// |r| <= pi/128), then the angle-addition formulas with the tabulated sin and
+// cos of (k mod 128) pi/64.
 __device__ __forceinline__ void sincos_tab(const MathTables& T, double x, double* sn,
                                            double* cs) {
-  constexpr double k32OverPi = 10.185916357881302;
-  constexpr double kP1 = 0.09817477042468103;
-  constexpr double kP2 = 3.827021247335479e-18;
-  constexpr double kP3 = -9.358655655369811e-35;
-  const double t = fma(x, k32OverPi, kShift);
+  constexpr double k64OverPi = 20.371832715762604;
+  constexpr double kP1 = 0.04908738521234052;
+  constexpr double kP2 = 1.9135106236677394e-18;
+  const double t = fma(x, k64OverPi, kShift);
   const double k = t - kShift;
   double r = fma(-k, kP1, x);
   r = fma(-k, kP2, r);
-  r = fma(-k, kP3, r);
-  const int idx = low_word(t) & 63;
+  const int idx = low_word(t) & 127;
   const lds_double* row = (const lds_double*)(&T.sc[idx][0]);
   const double sa = row[0], ca = row[1];
   const double r2 = r * r;
-  double ps = 2.7557319223985893e-06;          //  1/9!
-  ps = fma(ps, r2, -0.0001984126984126984);    // -1/7!
+  double ps = -0.0001984126984126984;          // -1/7!
   ps = fma(ps, r2, 0.008333333333333333);      //  1/5!
   ps = fma(ps, r2, -0.16666666666666666);      // -1/3!
   const double sr = fma(r * r2, ps, r);
-  double pc = 2.48015873015873e-05;            //  1/8!
-  pc = fma(pc, r2, -0.001388888888888889);     // -1/6!
+  double pc = -0.001388888888888889;           // -1/6!
   pc = fma(pc, r2, 0.041666666666666664);      //  1/4!
   pc = fma(pc, r2, -0.5);                      // -1/2
   const double cr = fma(r2, pc, 1.0);
@@ -140,9 +135,9 @@ __device__ __forceinline__ void sincos_tab(const MathTables& T, double x, double
 }
 
 // e^x: x = (64 m + j) ln2/64 + r with ln2/64 split in two doubles,
-// |r| <= ln2/128, Taylor polynomial of e^r to r^6 (truncation < 3e-20),
-// times the tabulated 2^(j/64), scaled by 2^m.  The argument is clamped to
-// [-746, 710] first: +inf above ~709.8, 0 below ~-745.
+// |r| <= ln2/128, Taylor polynomial of e^r to r^5 (truncation below 3.5e-17
+// relative), times the tabulated 2^(j/64), scaled by 2^m.  The argument is
+// clamped to [-746, 710] first: +inf above ~709.8, 0 below ~-745.
 __device__ __forceinline__ double exp_tab(const MathTables& T, double x) {
   constexpr double k64OverLn2 = 92.33248261689366;
   constexpr double kL1 = 0.010830424696249145;
@@ -155,8 +150,7 @@ __device__ __forceinline__ double exp_tab(const MathTables& T, double x) {
   const int ni = low_word(t);
   const int j = ni & 63;
   const int m = ni >> 6;  // floor(n / 64)
-  double p = 0.001388888888888889;   // 1/6!
-  p = fma(p, r, 0.008333333333333333);
+  double p = 0.008333333333333333;   // 1/5!
   p = fma(p, r, 0.041666666666666664);
   p = fma(p, r, 0.16666666666666666);
   p = fma(p, r, 0.5);

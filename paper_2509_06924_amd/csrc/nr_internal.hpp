@@ -73,7 +73,7 @@ struct KernelArgs {
   const float* constsf;  // workspace: their float copies (8 floats per row)
   // plan-owned constants (device): quadrature node offsets in units of
   // sigma_Q and normalised weights (kSmearNodes each), then the tables
-  // (sin, cos)(k pi/32) for k = 0..63 interleaved and 2^(j/64), j = 0..63
+  // (sin, cos)(k pi/64) for k = 0..127 interleaved and 2^(j/64), j = 0..63
   const double* rule;
   int zero_mask;  // always 0 (see the layer-record indexing in the kernels)
 };

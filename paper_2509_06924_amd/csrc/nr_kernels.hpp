@@ -116,31 +116,34 @@ __device__ __forceinline__ void stage_shared(Shared& s, int lane, const double* 
   const double* tb = rule + 2 * kSmearNodes;
   s.tab.sc[lane][0] = tb[2 * lane];
   s.tab.sc[lane][1] = tb[2 * lane + 1];
-  s.tab.e2[lane] = tb[128 + lane];
+  s.tab.sc[lane + 64][0] = tb[2 * lane + 128];
+  s.tab.sc[lane + 64][1] = tb[2 * lane + 129];
+  s.tab.e2[lane] = tb[256 + lane];
   __syncthreads();
 }
 
 // Interface quantities shared by the forward and adjoint sweeps.
 template <class Re>
 struct Iface {
-  cx<Re> s;   // 1/(kz_j + kz_{j+1})
-  cx<Re> r;   // Fresnel coefficient
+  cx<Re> s2;  // 1/(kz_j + kz_{j+1})^2
   cx<Re> f;   // Nevot-Croce factor
-  cx<Re> rp;  // r f
+  cx<Re> rp;  // r' = r f
   cx<Re> kk;  // kz_j kz_{j+1}
 };
 
+// r = (w_j - w_{j+1}) / (kz_j + kz_{j+1})^2 = N s^2.  For identical media
+// N = 0 and r = 0 exactly: s^2 stays finite because |kz| >= 1e-75 (the root's
+// guard), so no separate test is needed.
 template <class Re>
 __device__ __forceinline__ Iface<Re> interface_coeffs(const MathTables& T, cx<Re> kzc, cx<Re> kzn,
                                                       Re Nr, Re Ni, Re C) {
   Iface<Re> o;
-  o.s = crecip(kzc + kzn);
-  const cx<Re> s2 = o.s * o.s;
-  // identical media: r = 0 exactly (also avoids 0 * inf when both kz vanish)
-  o.r = (Nr == Re(0) && Ni == Re(0)) ? mk(Re(0), Re(0)) : mk(Nr, Ni) * s2;
+  const cx<Re> s = crecip(kzc + kzn);
+  o.s2 = s * s;
+  const cx<Re> r = mk(Nr, Ni) * o.s2;
   o.kk = kzc * kzn;
   o.f = cexp_tab(T, C * o.kk);
-  o.rp = o.r * o.f;
+  o.rp = r * o.f;
   return o;
 }
 
@@ -340,50 +343,88 @@ struct AdjStep {
   cx<Re> Pb, Qb;   // cotangents of the state entering level j
   cx<Re> kzb_c;    // contribution to kzbar_j
   cx<Re> kzb_n;    // contribution to kzbar_{j+1}
-  Re dd;           // dl/dd_j
-  Re ss;           // Re(conj(ubar) kz_j kz_{j+1})  (times -4 sigma_{j+1} later)
+  cx<Re> ub;       // cotangent of the Nevot-Croce exponent
+  cx<Re> w;        // conj(e) ebar (phase levels)
 };
 
+// conj(a) b + c and a b + c as four FMAs each.
+template <class Re>
+__device__ __forceinline__ cx<Re> cmulc_add(cx<Re> a, cx<Re> b, cx<Re> c) {
+  return mk(fma(a.re, b.re, fma(a.im, b.im, c.re)), fma(a.re, b.im, fma(-a.im, b.re, c.im)));
+}
+template <class Re>
+__device__ __forceinline__ cx<Re> cmul_add(cx<Re> a, cx<Re> b, cx<Re> c) {
+  return mk(fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im)));
+}
+
+// Per level (cotangent convention zbar = dl/dRe z + i dl/dIm z):
+//   t = r' P + Qv;  ebar = conj(t) Qbar;  tbar = conj(e) Qbar
+//   r'bar = conj(Qv) Pbar + conj(P) tbar;  Pbar_in = Pbar + conj(r') tbar;
+//   Qbar_in = conj(r') Pbar + tbar
+//   rbar = conj(f) r'bar;  ubar = conj(r') r'bar   (u = C kz_j kz_{j+1}, f = e^u)
+//   r = (kz_j - kz_{j+1}) s: dr/dkz_j = 2 kz_{j+1} s^2, dr/dkz_{j+1} = -2 kz_j s^2
+//   kzbar_j     += conj(kz_{j+1}) (C ubar + 2 conj(s^2) rbar)
+//   kzbar_{j+1} += conj(kz_j)     (C ubar - 2 conj(s^2) rbar)
+//   e = exp(-2 i kz d): with w = conj(e) ebar,
+//   kzbar_j += i D w  (D = 2d),   dl/dd = 2 Im(kz_j conj(w))
 template <class Re>
 __device__ __forceinline__ AdjStep<Re> adjoint_step(cx<Re> Ps, cx<Re> Qs, cx<Re> Pb, cx<Re> Qb,
                                                     cx<Re> kzc, cx<Re> kzn, const Iface<Re>& it,
                                                     Re C, bool has_phase, cx<Re> e, Re D) {
   using Cx = cx<Re>;
   AdjStep<Re> o;
-  const Cx t = it.rp * Ps + Qs;
-  Cx tb, eb = mk(Re(0), Re(0));
+  Cx tb;
+  o.w = mk(Re(0), Re(0));
   if (has_phase) {
-    eb = cmulc(t, Qb);
+    const Cx t = cmul_add(it.rp, Ps, Qs);
+    const Cx eb = cmulc(t, Qb);
     tb = cmulc(e, Qb);
+    o.w = cmulc(e, eb);
   } else {
     tb = Qb;
   }
-  // P_new = P + r' Qv ; t = r' P + Qv
-  const Cx rpb = cmulc(Qs, Pb) + cmulc(Ps, tb);
-  o.Pb = Pb + cmulc(it.rp, tb);
-  o.Qb = cmulc(it.rp, Pb) + tb;
-  // r' = r f, f = exp(C kz_j kz_{j+1})
+  const Cx rpb = cmulc_add(Ps, tb, cmulc(Qs, Pb));
+  o.Pb = cmulc_add(it.rp, tb, Pb);
+  o.Qb = cmulc_add(it.rp, Pb, tb);
   const Cx rb = cmulc(it.f, rpb);
-  const Cx ub = cmulc(it.rp, rpb);
-  o.ss = ub.re * it.kk.re + ub.im * it.kk.im;
-  // r = (kz_j - kz_{j+1}) s: dr/dkz_j = 2 kz_{j+1} s^2, dr/dkz_{j+1} = -2 kz_j s^2
-  const Cx s2 = it.s * it.s;
-  o.kzb_c = cmulc(C * kzn, ub) + cmulc(Re(2) * (kzn * s2), rb);
-  o.kzb_n = cmulc(C * kzc, ub) + cmulc(Re(-2) * (kzc * s2), rb);
-  o.dd = Re(0);
+  o.ub = cmulc(it.rp, rpb);
+  const Cx X = C * o.ub;
+  const Cx Y = cmulc(it.s2, rb);
+  const Cx Zc = mk(fma(Re(2), Y.re, X.re), fma(Re(2), Y.im, X.im));
+  const Cx Zn = mk(fma(Re(-2), Y.re, X.re), fma(Re(-2), Y.im, X.im));
+  o.kzb_c = cmulc(kzn, Zc);
+  o.kzb_n = cmulc(kzc, Zn);
   if (has_phase) {
-    // e = exp(-2 i kz d): de/dkz = -i D e, de/dd = -2 i kz e
-    o.kzb_c += cmulc(mk(D * e.im, -D * e.re), eb);
-    const Cx ze = kzc * e;
-    o.dd = eb.re * (Re(2) * ze.im) + eb.im * (Re(-2) * ze.re);
+    o.kzb_c.re = fma(-D, o.w.im, o.kzb_c.re);
+    o.kzb_c.im = fma(D, o.w.re, o.kzb_c.im);
   }
   return o;
 }
 
-// wbar = conj(dkz/dw) kzbar = conj(1/(2 kz)) kzbar = kz kzbar / (2 |kz|^2)
-template <class Re>
-__device__ __forceinline__ cx<Re> wbar_of(cx<Re> kz, Re inv_abs2, cx<Re> kzb) {
-  return (Re(0.5) * inv_abs2) * (kz * kzb);
+// acc += Re(conj(a) b), accumulated in FP64 (the sigma sums: a = ubar,
+// b = kz_j kz_{j+1}).
+__device__ __forceinline__ void acc_re_dot(double& acc, cd a, cd b) {
+  acc = fma(a.re, b.re, fma(a.im, b.im, acc));
+}
+__device__ __forceinline__ void acc_re_dot(double& acc, cf a, cf b) {
+  acc += (double)(a.re * b.re + a.im * b.im);
+}
+// acc += 2 Im(kz conj(w)) (the thickness derivative), in FP64.
+__device__ __forceinline__ void acc_dd(double& acc, cd kz, cd w) {
+  acc = fma(2.0, fma(kz.im, w.re, -(kz.re * w.im)), acc);
+}
+__device__ __forceinline__ void acc_dd(double& acc, cf kz, cf w) {
+  acc += 2.0 * (double)(kz.im * w.re - kz.re * w.im);
+}
+// acc += wbar = conj(dkz/dw) kzbar = conj(1/(2 kz)) kzbar = kz kzbar / (2 |kz|^2)
+__device__ __forceinline__ void acc_wbar(cd& acc, cd kz, double inv_abs2, cd kzb) {
+  const cd p = kz * kzb;
+  const double h = 0.5 * inv_abs2;
+  acc.re = fma(h, p.re, acc.re);
+  acc.im = fma(h, p.im, acc.im);
+}
+__device__ __forceinline__ void acc_wbar(cd& acc, cf kz, float inv_abs2, cf kzb) {
+  acc += widen((0.5f * inv_abs2) * (kz * kzb));
 }
 
 // Per-lane gradient accumulators for one point, FP64 in both precisions:
@@ -395,28 +436,22 @@ struct Accum {
 };
 
 // LDS tape of the store variant: per-lane state entering each level and the
-// layer phase, lane-minor.
-template <class Re>
-struct TapeEntry;
-template <>
-struct TapeEntry<double> {
-  using type = double2;
-};
-template <>
-struct TapeEntry<float> {
-  using type = float2;
-};
-
+// layer phase, as separate real and imaginary planes, lane-minor (a level's
+// two planes are 64 elements apart, one ds_write2/ds_read2 per value).
 template <class Re, int LMAX>
 struct GradTape {
-  using V = typename TapeEntry<Re>::type;
-  V P[LMAX + 1][64], Qv[LMAX + 1][64], E[LMAX + 1][64];
+  Re P[LMAX + 1][2][64], Qv[LMAX + 1][2][64], E[LMAX + 1][2][64];
 };
 
-__device__ __forceinline__ double2 to_v2(cd z) { return make_double2(z.re, z.im); }
-__device__ __forceinline__ float2 to_v2(cf z) { return make_float2(z.re, z.im); }
-__device__ __forceinline__ cd from_v2(double2 v) { return mk(v.x, v.y); }
-__device__ __forceinline__ cf from_v2(float2 v) { return mk(v.x, v.y); }
+template <class Re>
+__device__ __forceinline__ void tape_put(Re (&slot)[2][64], int lane, cx<Re> z) {
+  slot[0][lane] = z.re;
+  slot[1][lane] = z.im;
+}
+template <class Re>
+__device__ __forceinline__ cx<Re> tape_get(const Re (&slot)[2][64], int lane) {
+  return mk(slot[0][lane], slot[1][lane]);
+}
 
 // ---------------------------------------------------------------------------
 // One node, store variant: forward with the tape in LDS and kz in registers,
@@ -452,13 +487,13 @@ __device__ __forceinline__ double node_grad_store(const MathTables& T, const Lay
       const Iface<Re> it =
           interface_coeffs(T, kz[jj], kz[jj + 1], L.Nr(jj), L.Ni(jj), L.C(jj));
       ifc[jj] = it;
-      tp.P[jj][lane] = to_v2(Pv);
-      tp.Qv[jj][lane] = to_v2(Qv);
+      tape_put(tp.P[jj], lane, Pv);
+      tape_put(tp.Qv[jj], lane, Qv);
       const Cx Pn = Pv + it.rp * Qv;
       const Cx t = it.rp * Pv + Qv;
       if (jj >= 1) {
         const Cx e = layer_phase(T, kz[jj], L.D(jj));
-        tp.E[jj][lane] = to_v2(e);
+        tape_put(tp.E[jj], lane, e);
         Qv = e * t;
       } else {
         Qv = t;
@@ -477,19 +512,19 @@ __device__ __forceinline__ double node_grad_store(const MathTables& T, const Lay
     if (jj <= N) {
       const Re C = L.C(jj);
       const Iface<Re>& it = ifc[jj];
-      const Cx Ps = from_v2(tp.P[jj][lane]);
-      const Cx Qs = from_v2(tp.Qv[jj][lane]);
+      const Cx Ps = tape_get(tp.P[jj], lane);
+      const Cx Qs = tape_get(tp.Qv[jj], lane);
       const bool ph = jj >= 1;
-      const Cx e = ph ? from_v2(tp.E[jj][lane]) : mk(Re(1), Re(0));
+      const Cx e = ph ? tape_get(tp.E[jj], lane) : mk(Re(1), Re(0));
       const AdjStep<Re> st =
           adjoint_step(Ps, Qs, Pb, Qb, kz[jj], kz[jj + 1], it, C, ph, e, ph ? L.D(jj) : Re(0));
       kzbc += st.kzb_c;
-      acc.Hs[jj + 1] += (double)st.ss;
+      acc_re_dot(acc.Hs[jj + 1], st.ub, it.kk);
       if (ph) {
-        acc.Hd[jj] += (double)st.dd;
-        acc.Hw[jj] += widen(wbar_of(kz[jj], ia[jj], kzbc));
+        acc_dd(acc.Hd[jj], kz[jj], st.w);
+        acc_wbar(acc.Hw[jj], kz[jj], ia[jj], kzbc);
       }
-      if (jj == N) acc.Hw[jj + 1] += widen(wbar_of(kz[jj + 1], ia[jj + 1], st.kzb_n));
+      if (jj == N) acc_wbar(acc.Hw[jj + 1], kz[jj + 1], ia[jj + 1], st.kzb_n);
       Pb = st.Pb;
       Qb = st.Qb;
       kzbc = st.kzb_n;
@@ -547,12 +582,12 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
       const Cx e = ph ? layer_phase(T, kzc, D) : mk(Re(1), Re(0));
       const AdjStep<Re> st = adjoint_step(tapeP[jj], tapeQ[jj], Pb, Qb, kzc, rn.kz, it, C, ph, e, D);
       kzbc += st.kzb_c;
-      acc.Hs[jj + 1] += (double)st.ss;
+      acc_re_dot(acc.Hs[jj + 1], st.ub, it.kk);
       if (ph) {
-        acc.Hd[jj] += (double)st.dd;
-        acc.Hw[jj] += widen(wbar_of(kzc, iac, kzbc));
+        acc_dd(acc.Hd[jj], kzc, st.w);
+        acc_wbar(acc.Hw[jj], kzc, iac, kzbc);
       }
-      if (jj == N) acc.Hw[jj + 1] += widen(wbar_of(rn.kz, rn.inv_abs2, st.kzb_n));
+      if (jj == N) acc_wbar(acc.Hw[jj + 1], rn.kz, rn.inv_abs2, st.kzb_n);
       Pb = st.Pb;
       Qb = st.Qb;
       kzc = rn.kz;
