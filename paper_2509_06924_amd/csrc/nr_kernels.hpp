@@ -42,13 +42,26 @@
 namespace nr {
 
 // Precision policies of the layer product.
+// kSlimMax: the deepest bucket whose store variant keeps only s^2 and f per
+// interface in registers and re-forms r' and kz_j kz_{j+1} in the adjoint
+// (8 more FMAs per level, 8 fewer registers).  Measured on MI355X: in FP64 it
+// lifts LMAX = 6 to two waves per SIMD (0.43 -> 0.45 of peak) but slows
+// LMAX = 10 (3.49 -> 3.53 ms on the 4096-draw batch); FP32 has registers to
+// spare and only loses.
+//
+// min_waves(LMAX): the waves per SIMD the gradient kernel is compiled for (its
+// register budget is 512 / min_waves per lane).
 struct F64 {
   using real = double;
   static constexpr int kStoreMax = kStoreMaxLayers;
+  static constexpr int kSlimMax = 6;
+  static constexpr int min_waves(int) { return 1; }
 };
 struct F32 {
   using real = float;
   static constexpr int kStoreMax = kStoreMaxLayersF32;
+  static constexpr int kSlimMax = 0;
+  static constexpr int min_waves(int lmax) { return lmax <= 10 ? 2 : 1; }
 };
 
 // ---------------------------------------------------------------------------
@@ -61,7 +74,8 @@ struct F32 {
 //   Nr + i Ni = w_m - w_{m+1} = (A_{m+1} - A_m) + i (B_{m+1} - B_m), the
 //        Q-independent numerator of r_m = (w_m - w_{m+1}) / (kz_m + kz_{m+1})^2
 //   C  = -2 sigma_{m+1}^2                  (Nevot-Croce exponent factor)
-//   D  = 2 d_m                             (layers 1..N)
+//   D  = 2 d_m                             (layers 1..N; 0 for the fronting
+//                                           and the backing)
 // and eight floats: B, Nr, Ni, C, D rounded to float, then padding (the FP32
 // variant reads A from the doubles: kz0^2 - A is formed in FP64).
 // Interface fields of the backing record are 0.
@@ -74,6 +88,14 @@ constexpr int kRecF = kRecFloats;
 // far as the compiler can tell, so the records are re-read (with scalar
 // loads) inside the node loop instead of being hoisted out of it, which would
 // need far more scalar registers than exist.
+//
+// Media below the backing (m > N + 1, used when an item is evaluated at its
+// bucket's depth LMAX > N) read the backing's record: the same wavevector,
+// a zero interface numerator, sigma 0 and thickness 0 (k_item_consts stores
+// D = 0 for the backing).  Such a medium is an exact copy of the backing
+// joined by r' = 0, so the state below the backing stays (1, 0) and the
+// forward product is unchanged; in the adjoint the copies are the backing's
+// own parameters, and their w-cotangents are added to the backing's.
 template <class P>
 struct Layers {
   using Re = typename P::real;
@@ -81,12 +103,14 @@ struct Layers {
   const double* rec;   // the item's double records
   const float* recf;   // the item's float records
   int z;               // an opaque zero
-  __device__ __forceinline__ double at(int m, int f) const { return rec[(m + z) * kRec + f]; }
+  int nb;              // the backing medium, N + 1
+  __device__ __forceinline__ int med(int m) const { return (m < nb ? m : nb) + z; }
+  __device__ __forceinline__ double at(int m, int f) const { return rec[med(m) * kRec + f]; }
   __device__ __forceinline__ Re get(int m, int fd, int ff) const {
     if constexpr (kF64)
       return at(m, fd);
     else
-      return recf[(m + z) * kRecF + ff];
+      return recf[med(m) * kRecF + ff];
   }
   __device__ __forceinline__ double A(int m) const { return at(m, 0); }
   __device__ __forceinline__ Re B(int m) const { return get(m, 1, 0); }
@@ -244,11 +268,12 @@ __device__ __forceinline__ WuInfo tail_setup(const KernelArgs& a, int w, int lan
 }
 
 template <class P>
-__device__ __forceinline__ Layers<P> item_layers(const KernelArgs& a, int64_t roff, int k) {
+__device__ __forceinline__ Layers<P> item_layers(const KernelArgs& a, int64_t roff, int N, int k) {
   Layers<P> L;
   L.rec = a.consts + roff * kRec;
   L.recf = a.constsf + roff * kRecF;
   L.z = k & a.zero_mask;
+  L.nb = N + 1;
   return L;
 }
 
@@ -274,7 +299,7 @@ __global__ __launch_bounds__(64) void k_reflectivity(KernelArgs a) {
     const double q = (K == 1) ? u.Q : smear_node(u.Q, u.dqq, ld(s.t[k]));
     badq |= !(q > 0.0);
     const double wk = (K == 1) ? 1.0 : ld(s.w[k]);
-    Rsm += wk * node_reflectivity(s.tab, item_layers<P>(a, u.roff, k), u.N, q);
+    Rsm += wk * node_reflectivity(s.tab, item_layers<P>(a, u.roff, u.N, k), u.N, q);
   }
   if (u.active) {
     double Rhat = a.scale[u.item] * Rsm + a.bkg[u.item];
@@ -318,7 +343,7 @@ __global__ __launch_bounds__(64) void k_loglik(KernelArgs a) {
     const double q = (K == 1) ? u.Q : smear_node(u.Q, u.dqq, ld(s.t[k]));
     badq |= !(q > 0.0);
     const double wk = (K == 1) ? 1.0 : ld(s.w[k]);
-    Rsm += wk * node_reflectivity(s.tab, item_layers<P>(a, u.roff, k), u.N, q);
+    Rsm += wk * node_reflectivity(s.tab, item_layers<P>(a, u.roff, u.N, k), u.N, q);
   }
   double ll = 0.0;
   uint32_t bits = 0;
@@ -460,46 +485,55 @@ __device__ __forceinline__ cx<Re> tape_get(const Re (&slot)[2][64], int lane) {
 template <class P, int LMAX>
 __device__ __forceinline__ double node_grad_store(const MathTables& T, const Layers<P>& L,
                                                   GradTape<typename P::real, LMAX>& tp,
-                                                  Accum<LMAX>& acc, int N, int lane, double q,
+                                                  Accum<LMAX>& acc, int lane, double q,
                                                   double wk) {
   using Re = typename P::real;
   using Cx = cx<Re>;
   const double kz0sq = kz0_squared(q);
   Cx kz[LMAX + 2];
   Re ia[LMAX + 2];
-  Iface<Re> ifc[LMAX + 1];
+  // per interface, kept for the adjoint: s^2 and the Nevot-Croce factor f,
+  // and unless the bucket is slim, r' and kz_j kz_{j+1} too
+  constexpr bool kSlim = LMAX <= P::kSlimMax;
+  Cx ks2[LMAX + 1], kf[LMAX + 1];
+  Cx krp[kSlim ? 1 : LMAX + 1], kkk[kSlim ? 1 : LMAX + 1];
   Cx Pv = mk(Re(1), Re(0)), Qv = mk(Re(0), Re(0));
+  {
+    const RootT<Re> rt = medium_root(L, kz0sq, LMAX + 1);
+    kz[LMAX + 1] = rt.kz;
+    ia[LMAX + 1] = rt.inv_abs2;
+  }
+  // every level is evaluated (the depth is the bucket's), so the whole node
+  // is straight-line code the scheduler can interleave across levels
 #pragma unroll
-  for (int jj = LMAX + 1; jj >= 0; --jj) {
-    if (jj == N + 1) {
+  for (int jj = LMAX; jj >= 0; --jj) {
+    if (jj == 0) {
+      kz[0] = fronting_kz<P>(q);
+      ia[0] = Re(0);
+    } else {
       const RootT<Re> rt = medium_root(L, kz0sq, jj);
       kz[jj] = rt.kz;
       ia[jj] = rt.inv_abs2;
-    } else if (jj <= N) {
-      if (jj == 0) {
-        kz[0] = fronting_kz<P>(q);
-        ia[0] = Re(0);
-      } else {
-        const RootT<Re> rt = medium_root(L, kz0sq, jj);
-        kz[jj] = rt.kz;
-        ia[jj] = rt.inv_abs2;
-      }
-      const Iface<Re> it =
-          interface_coeffs(T, kz[jj], kz[jj + 1], L.Nr(jj), L.Ni(jj), L.C(jj));
-      ifc[jj] = it;
-      tape_put(tp.P[jj], lane, Pv);
-      tape_put(tp.Qv[jj], lane, Qv);
-      const Cx Pn = Pv + it.rp * Qv;
-      const Cx t = it.rp * Pv + Qv;
-      if (jj >= 1) {
-        const Cx e = layer_phase(T, kz[jj], L.D(jj));
-        tape_put(tp.E[jj], lane, e);
-        Qv = e * t;
-      } else {
-        Qv = t;
-      }
-      Pv = Pn;
     }
+    const Iface<Re> it = interface_coeffs(T, kz[jj], kz[jj + 1], L.Nr(jj), L.Ni(jj), L.C(jj));
+    ks2[jj] = it.s2;
+    kf[jj] = it.f;
+    if constexpr (!kSlim) {
+      krp[jj] = it.rp;
+      kkk[jj] = it.kk;
+    }
+    tape_put(tp.P[jj], lane, Pv);
+    tape_put(tp.Qv[jj], lane, Qv);
+    const Cx Pn = Pv + it.rp * Qv;
+    const Cx t = it.rp * Pv + Qv;
+    if (jj >= 1) {
+      const Cx e = layer_phase(T, kz[jj], L.D(jj));
+      tape_put(tp.E[jj], lane, e);
+      Qv = e * t;
+    } else {
+      Qv = t;
+    }
+    Pv = Pn;
   }
   const Cx iP = crecip(Pv);
   const Cx r = Qv * iP;
@@ -509,26 +543,33 @@ __device__ __forceinline__ double node_grad_store(const MathTables& T, const Lay
   Cx kzbc = mk(Re(0), Re(0));
 #pragma unroll
   for (int jj = 0; jj <= LMAX; ++jj) {
-    if (jj <= N) {
-      const Re C = L.C(jj);
-      const Iface<Re>& it = ifc[jj];
-      const Cx Ps = tape_get(tp.P[jj], lane);
-      const Cx Qs = tape_get(tp.Qv[jj], lane);
-      const bool ph = jj >= 1;
-      const Cx e = ph ? tape_get(tp.E[jj], lane) : mk(Re(1), Re(0));
-      const AdjStep<Re> st =
-          adjoint_step(Ps, Qs, Pb, Qb, kz[jj], kz[jj + 1], it, C, ph, e, ph ? L.D(jj) : Re(0));
-      kzbc += st.kzb_c;
-      acc_re_dot(acc.Hs[jj + 1], st.ub, it.kk);
-      if (ph) {
-        acc_dd(acc.Hd[jj], kz[jj], st.w);
-        acc_wbar(acc.Hw[jj], kz[jj], ia[jj], kzbc);
-      }
-      if (jj == N) acc_wbar(acc.Hw[jj + 1], kz[jj + 1], ia[jj + 1], st.kzb_n);
-      Pb = st.Pb;
-      Qb = st.Qb;
-      kzbc = st.kzb_n;
+    const Re C = L.C(jj);
+    Iface<Re> it;
+    it.s2 = ks2[jj];
+    it.f = kf[jj];
+    if constexpr (kSlim) {
+      it.rp = (mk(L.Nr(jj), L.Ni(jj)) * it.s2) * it.f;
+      it.kk = kz[jj] * kz[jj + 1];
+    } else {
+      it.rp = krp[jj];
+      it.kk = kkk[jj];
     }
+    const Cx Ps = tape_get(tp.P[jj], lane);
+    const Cx Qs = tape_get(tp.Qv[jj], lane);
+    const bool ph = jj >= 1;
+    const Cx e = ph ? tape_get(tp.E[jj], lane) : mk(Re(1), Re(0));
+    const AdjStep<Re> st =
+        adjoint_step(Ps, Qs, Pb, Qb, kz[jj], kz[jj + 1], it, C, ph, e, ph ? L.D(jj) : Re(0));
+    kzbc += st.kzb_c;
+    acc_re_dot(acc.Hs[jj + 1], st.ub, it.kk);
+    if (ph) {
+      acc_dd(acc.Hd[jj], kz[jj], st.w);
+      acc_wbar(acc.Hw[jj], kz[jj], ia[jj], kzbc);
+    }
+    if (jj == LMAX) acc_wbar(acc.Hw[jj + 1], kz[jj + 1], ia[jj + 1], st.kzb_n);
+    Pb = st.Pb;
+    Qb = st.Qb;
+    kzbc = st.kzb_n;
   }
   return (double)cabs2(r);
 }
@@ -539,28 +580,25 @@ __device__ __forceinline__ double node_grad_store(const MathTables& T, const Lay
 // ---------------------------------------------------------------------------
 template <class P, int LMAX>
 __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const Layers<P>& L,
-                                                      Accum<LMAX>& acc, int N, double q,
-                                                      double wk) {
+                                                      Accum<LMAX>& acc, double q, double wk) {
   using Re = typename P::real;
   using Cx = cx<Re>;
   const double kz0sq = kz0_squared(q);
   const Cx kz0 = fronting_kz<P>(q);
   Cx tapeP[LMAX + 1], tapeQ[LMAX + 1];
-  Cx kzn = medium_root(L, kz0sq, N + 1).kz;
+  Cx kzn = medium_root(L, kz0sq, LMAX + 1).kz;
   Cx Pv = mk(Re(1), Re(0)), Qv = mk(Re(0), Re(0));
 #pragma unroll
   for (int jj = LMAX; jj >= 0; --jj) {
-    if (jj <= N) {
-      const Cx kzc = (jj == 0) ? kz0 : medium_root(L, kz0sq, jj).kz;
-      tapeP[jj] = Pv;
-      tapeQ[jj] = Qv;
-      const Iface<Re> it = interface_coeffs(T, kzc, kzn, L.Nr(jj), L.Ni(jj), L.C(jj));
-      const Cx Pn = Pv + it.rp * Qv;
-      const Cx t = it.rp * Pv + Qv;
-      Qv = (jj >= 1) ? layer_phase(T, kzc, L.D(jj)) * t : t;
-      Pv = Pn;
-      kzn = kzc;
-    }
+    const Cx kzc = (jj == 0) ? kz0 : medium_root(L, kz0sq, jj).kz;
+    tapeP[jj] = Pv;
+    tapeQ[jj] = Qv;
+    const Iface<Re> it = interface_coeffs(T, kzc, kzn, L.Nr(jj), L.Ni(jj), L.C(jj));
+    const Cx Pn = Pv + it.rp * Qv;
+    const Cx t = it.rp * Pv + Qv;
+    Qv = (jj >= 1) ? layer_phase(T, kzc, L.D(jj)) * t : t;
+    Pv = Pn;
+    kzn = kzc;
     __builtin_amdgcn_sched_barrier(0x0100);  // only LDS reads may move across
   }
   const Cx iP = crecip(Pv);
@@ -573,27 +611,25 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
   Cx kzbc = mk(Re(0), Re(0));
 #pragma unroll
   for (int jj = 0; jj <= LMAX; ++jj) {
-    if (jj <= N) {
-      const RootT<Re> rn = medium_root(L, kz0sq, jj + 1);
-      const Re C = L.C(jj);
-      const Iface<Re> it = interface_coeffs(T, kzc, rn.kz, L.Nr(jj), L.Ni(jj), C);
-      const bool ph = jj >= 1;
-      const Re D = ph ? L.D(jj) : Re(0);
-      const Cx e = ph ? layer_phase(T, kzc, D) : mk(Re(1), Re(0));
-      const AdjStep<Re> st = adjoint_step(tapeP[jj], tapeQ[jj], Pb, Qb, kzc, rn.kz, it, C, ph, e, D);
-      kzbc += st.kzb_c;
-      acc_re_dot(acc.Hs[jj + 1], st.ub, it.kk);
-      if (ph) {
-        acc_dd(acc.Hd[jj], kzc, st.w);
-        acc_wbar(acc.Hw[jj], kzc, iac, kzbc);
-      }
-      if (jj == N) acc_wbar(acc.Hw[jj + 1], rn.kz, rn.inv_abs2, st.kzb_n);
-      Pb = st.Pb;
-      Qb = st.Qb;
-      kzc = rn.kz;
-      iac = rn.inv_abs2;
-      kzbc = st.kzb_n;
+    const RootT<Re> rn = medium_root(L, kz0sq, jj + 1);
+    const Re C = L.C(jj);
+    const Iface<Re> it = interface_coeffs(T, kzc, rn.kz, L.Nr(jj), L.Ni(jj), C);
+    const bool ph = jj >= 1;
+    const Re D = ph ? L.D(jj) : Re(0);
+    const Cx e = ph ? layer_phase(T, kzc, D) : mk(Re(1), Re(0));
+    const AdjStep<Re> st = adjoint_step(tapeP[jj], tapeQ[jj], Pb, Qb, kzc, rn.kz, it, C, ph, e, D);
+    kzbc += st.kzb_c;
+    acc_re_dot(acc.Hs[jj + 1], st.ub, it.kk);
+    if (ph) {
+      acc_dd(acc.Hd[jj], kzc, st.w);
+      acc_wbar(acc.Hw[jj], kzc, iac, kzbc);
     }
+    if (jj == LMAX) acc_wbar(acc.Hw[jj + 1], rn.kz, rn.inv_abs2, st.kzb_n);
+    Pb = st.Pb;
+    Qb = st.Qb;
+    kzc = rn.kz;
+    iac = rn.inv_abs2;
+    kzbc = st.kzb_n;
     __builtin_amdgcn_sched_barrier(0x0100);  // only LDS reads may move across
   }
   return (double)cabs2(r);
@@ -609,7 +645,7 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
 //   [3 + 3NR + m]  sum Re(conj(ubar) kz_{m-1} kz_m)   (sigma_m factor applied later)
 // ---------------------------------------------------------------------------
 template <class P, int LMAX, bool STORE, bool TAIL>
-__global__ __launch_bounds__(64) void k_loglik_grad(KernelArgs a) {
+__global__ __launch_bounds__(64, P::min_waves(LMAX)) void k_loglik_grad(KernelArgs a) {
   using Re = typename P::real;
   __shared__ Shared s;
   using Tape = typename std::conditional<STORE, GradTape<Re, LMAX>, char>::type;
@@ -635,13 +671,24 @@ __global__ __launch_bounds__(64) void k_loglik_grad(KernelArgs a) {
     const double q = (K == 1) ? u.Q : smear_node(u.Q, u.dqq, ld(s.t[k]));
     badq |= !(q > 0.0);
     const double wk = (K == 1) ? 1.0 : ld(s.w[k]);
-    const Layers<P> L = item_layers<P>(a, u.roff, k);
+    const Layers<P> L = item_layers<P>(a, u.roff, N, k);
     double R;
     if constexpr (STORE)
-      R = node_grad_store<P, LMAX>(s.tab, L, tape, acc, N, lane, q, wk);
+      R = node_grad_store<P, LMAX>(s.tab, L, tape, acc, lane, q, wk);
     else
-      R = node_grad_recompute<P, LMAX>(s.tab, L, acc, N, q, wk);
+      R = node_grad_recompute<P, LMAX>(s.tab, L, acc, q, wk);
     Rsm += wk * R;
+  }
+  // the item was evaluated at depth LMAX: the copies of the backing below it
+  // (media N + 2 .. LMAX + 1) are the backing's parameters
+  {
+    cd back = mk(0.0, 0.0);
+#pragma unroll
+    for (int m = 1; m < LMAX + 2; ++m)
+      if (m >= N + 1) back += acc.Hw[m];
+#pragma unroll
+    for (int m = 1; m < LMAX + 2; ++m)
+      if (m == N + 1) acc.Hw[m] = back;
   }
 
   // ---- instrument, likelihood, seeds ----

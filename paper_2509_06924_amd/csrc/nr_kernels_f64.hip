@@ -32,7 +32,8 @@ __global__ __launch_bounds__(64) void k_item_consts(const int64_t* row_off, cons
     v[3] = 0.0;
     v[4] = 0.0;
   }
-  v[5] = 2.0 * rows[4 * m];
+  // the fronting and backing have no thickness (their rows' d is ignored)
+  v[5] = (m == 0 || m + 1 == NR) ? 0.0 : 2.0 * rows[4 * m];
   double* out = rec + (r0 + m) * kRecDoubles;
   for (int f = 0; f < kRecDoubles; ++f) out[f] = v[f];
   float* outf = recf + (r0 + m) * kRecFloats;
