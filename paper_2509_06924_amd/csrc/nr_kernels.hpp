@@ -56,12 +56,21 @@ struct F64 {
   static constexpr int kStoreMax = kStoreMaxLayers;
   static constexpr int kSlimMax = 6;
   static constexpr int min_waves(int) { return 1; }
+  // recompute variant: levels whose phase and Nevot-Croce factor are kept in
+  // LDS (2 KB per level per wave; ~36 KB of the 40 KB a wave may use at one
+  // wave per SIMD)
+  static constexpr int ef_levels(int lmax) { return lmax + 1 < 17 ? lmax + 1 : 17; }
 };
 struct F32 {
   using real = float;
   static constexpr int kStoreMax = kStoreMaxLayersF32;
   static constexpr int kSlimMax = 0;
   static constexpr int min_waves(int lmax) { return lmax <= 10 ? 2 : 1; }
+  // 1 KB per level; up to 16 layers the kernel keeps two waves per SIMD, so
+  // its LDS stays within 20 KB
+  static constexpr int ef_levels(int lmax) {
+    return lmax <= 16 ? (lmax + 1 < 16 ? lmax + 1 : 16) : (lmax + 1 < 35 ? lmax + 1 : 35);
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -574,13 +583,23 @@ __device__ __forceinline__ double node_grad_store(const MathTables& T, const Lay
   return (double)cabs2(r);
 }
 
+// LDS cache of the recompute variant: for levels 0..KS-1, the layer phase e
+// and the Nevot-Croce factor f (planes e.re, e.im, f.re, f.im, lane-minor).
+template <class Re, int KS>
+struct EfCache {
+  Re v[KS][4][64];
+};
+
 // ---------------------------------------------------------------------------
 // One node, recompute variant: the state tape stays in registers; the adjoint
-// recomputes each medium's wavevector and each layer's phase.
+// recomputes each medium's wavevector and interface reciprocal, and, below
+// the KS cached levels, the phase and Nevot-Croce factor too.
 // ---------------------------------------------------------------------------
-template <class P, int LMAX>
+template <class P, int LMAX, int KS>
 __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const Layers<P>& L,
-                                                      Accum<LMAX>& acc, double q, double wk) {
+                                                      EfCache<typename P::real, KS>& ef,
+                                                      Accum<LMAX>& acc, int lane, double q,
+                                                      double wk) {
   using Re = typename P::real;
   using Cx = cx<Re>;
   const double kz0sq = kz0_squared(q);
@@ -596,7 +615,14 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
     const Iface<Re> it = interface_coeffs(T, kzc, kzn, L.Nr(jj), L.Ni(jj), L.C(jj));
     const Cx Pn = Pv + it.rp * Qv;
     const Cx t = it.rp * Pv + Qv;
-    Qv = (jj >= 1) ? layer_phase(T, kzc, L.D(jj)) * t : t;
+    const Cx e = (jj >= 1) ? layer_phase(T, kzc, L.D(jj)) : mk(Re(1), Re(0));
+    if (jj < KS) {
+      ef.v[jj][0][lane] = e.re;
+      ef.v[jj][1][lane] = e.im;
+      ef.v[jj][2][lane] = it.f.re;
+      ef.v[jj][3][lane] = it.f.im;
+    }
+    Qv = (jj >= 1) ? e * t : t;
     Pv = Pn;
     kzn = kzc;
     __builtin_amdgcn_sched_barrier(0x0100);  // only LDS reads may move across
@@ -613,10 +639,21 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
   for (int jj = 0; jj <= LMAX; ++jj) {
     const RootT<Re> rn = medium_root(L, kz0sq, jj + 1);
     const Re C = L.C(jj);
-    const Iface<Re> it = interface_coeffs(T, kzc, rn.kz, L.Nr(jj), L.Ni(jj), C);
     const bool ph = jj >= 1;
     const Re D = ph ? L.D(jj) : Re(0);
-    const Cx e = ph ? layer_phase(T, kzc, D) : mk(Re(1), Re(0));
+    Iface<Re> it;
+    Cx e;
+    if (jj < KS) {
+      const Cx s = crecip(kzc + rn.kz);
+      it.s2 = s * s;
+      it.f = mk(ef.v[jj][2][lane], ef.v[jj][3][lane]);
+      it.rp = (mk(L.Nr(jj), L.Ni(jj)) * it.s2) * it.f;
+      it.kk = kzc * rn.kz;
+      e = ph ? mk(ef.v[jj][0][lane], ef.v[jj][1][lane]) : mk(Re(1), Re(0));
+    } else {
+      it = interface_coeffs(T, kzc, rn.kz, L.Nr(jj), L.Ni(jj), C);
+      e = ph ? layer_phase(T, kzc, D) : mk(Re(1), Re(0));
+    }
     const AdjStep<Re> st = adjoint_step(tapeP[jj], tapeQ[jj], Pb, Qb, kzc, rn.kz, it, C, ph, e, D);
     kzbc += st.kzb_c;
     acc_re_dot(acc.Hs[jj + 1], st.ub, it.kk);
@@ -650,6 +687,9 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX)) void k_loglik_grad(KernelAr
   __shared__ Shared s;
   using Tape = typename std::conditional<STORE, GradTape<Re, LMAX>, char>::type;
   __shared__ Tape tape;
+  constexpr int KS = STORE ? 1 : P::ef_levels(LMAX);
+  using Ef = typename std::conditional<STORE, char, EfCache<Re, KS>>::type;
+  __shared__ Ef efc;
   const int lane = threadIdx.x;
   const int w = blockIdx.x;
   const WuInfo u = TAIL ? tail_setup(a, w, lane) : wu_setup(a, w, lane);
@@ -676,7 +716,7 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX)) void k_loglik_grad(KernelAr
     if constexpr (STORE)
       R = node_grad_store<P, LMAX>(s.tab, L, tape, acc, lane, q, wk);
     else
-      R = node_grad_recompute<P, LMAX>(s.tab, L, acc, q, wk);
+      R = node_grad_recompute<P, LMAX, KS>(s.tab, L, efc, acc, lane, q, wk);
     Rsm += wk * R;
   }
   // the item was evaluated at depth LMAX: the copies of the backing below it
