@@ -157,6 +157,10 @@ def main():
                     help="skip the forward-only and per-item (unbatched) rows")
     ap.add_argument("--no-other-workloads", action="store_true",
                     help="skip the single-film, co-fit, ragged-HMC and VI rows")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's default schedule instead of the autotuned one")
+    ap.add_argument("--autotune-cache", default=None,
+                    help="JSON cache of autotuned schedules (default: the user cache)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=float, default=0.0,
                     help="only run a plain device copy of this size (counter calibration)")
@@ -188,7 +192,11 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     batch, cfg = make_workload(args.workload)
-    prob = nr.Problem.from_batch(batch, device="cuda:0")
+    schedule = None
+    if not args.no_autotune:
+        from paper_2509_06924_amd import autotune
+        schedule = autotune.tune(batch, device="cuda:0", cache=args.autotune_cache)
+    prob = nr.Problem.from_batch(batch, device="cuda:0", options=schedule)
     out = (torch.empty(batch.n_items, dtype=torch.float64, device="cuda:0"),
            torch.empty_like(prob.layers),
            torch.empty(batch.n_items, 2, dtype=torch.float64, device="cuda:0"))
@@ -236,6 +244,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded stand-in; the paper's datasets are not available)",
         "config": cfg,
+        "schedule": schedule or "library default",
         "layer_steps_per_step": layer_steps,
         "draw_q_per_s": batch.data_points() * args.steps / wall,
         "finite": ok,
@@ -254,7 +263,8 @@ def main():
     if not args.no_extra_rows:
         rec["forward_only"] = forward_only_row(prob, batch, args.steps)
         rec["plain_unbatched"] = plain_unbatched_row(nr, batch)
-        rec["fp32"] = fp32_row(nr, batch, out, args.steps, hip)
+        rec["fp32"] = fp32_row(nr, batch, out, args.steps, hip,
+                               None if args.no_autotune else args.autotune_cache or "")
     if not args.no_extra_rows and args.workload == "c2" and not args.no_other_workloads:
         rec["other_workloads"] = other_workloads(nr)
     if not args.no_cpu_baseline:
@@ -277,15 +287,21 @@ def forward_only_row(prob, batch, steps):
             "what": "nr_loglik on the same batch (forward only)"}
 
 
-def fp32_row(nr, batch, out64, steps, hip):
+def fp32_row(nr, batch, out64, steps, hip, tune_cache=None):
     """The FP32 variant on the same workload: time, rate, fraction of the FP32
     VALU peak, and its largest deviation from the FP64 path (which matches the
-    oracle to 1e-10 / 1e-8), over every item."""
+    oracle to 1e-10 / 1e-8), over every item.  tune_cache None: library
+    default schedule; else autotuned ("" = the user cache)."""
     import numpy as np
     import torch
 
     from paper_2509_06924_amd import _native
-    prob = nr.Problem.from_batch(batch, device="cuda:0", precision=nr.NR_F32)
+    schedule = None
+    if tune_cache is not None:
+        from paper_2509_06924_amd import autotune
+        schedule = autotune.tune(batch, precision=nr.NR_F32, device="cuda:0",
+                                 cache=tune_cache or None)
+    prob = nr.Problem.from_batch(batch, device="cuda:0", precision=nr.NR_F32, options=schedule)
     out = (torch.empty_like(out64[0]), torch.empty_like(out64[1]), torch.empty_like(out64[2]))
     stream = torch.cuda.current_stream()
     for _ in range(2):
@@ -318,7 +334,7 @@ def fp32_row(nr, batch, out64, steps, hip):
         gerr = max(gerr, float(np.max(np.abs(a - o)) / np.max(np.abs(o))))
     achieved = FLOP_PER_LAYER_STEP * batch.layer_steps() / kern_s
     return {"value": batch.layer_steps() / dt, "unit": UNIT, "ms_per_step": dt * 1e3,
-            "kernel_ms": kern_s * 1e3, "dtype": "f32",
+            "kernel_ms": kern_s * 1e3, "dtype": "f32", "schedule": schedule or "library default",
             "achieved_tflops": achieved / 1e12, "peak_tflops": FP32_VALU_PEAK / 1e12,
             "frac": achieved / FP32_VALU_PEAK,
             "max_rel_err_logL": float(np.max(np.abs(ll32 - ll64) / np.abs(ll64))),

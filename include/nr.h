@@ -126,6 +126,49 @@ const char* nr_status_string(nr_status status);
  * memory (owned by the plan; released by nr_plan_destroy).  Synchronous. */
 nr_status nr_plan_create(const nr_batch_desc* desc, nr_plan** plan_out);
 
+/* Plan tuning options (nr_plan_create_ex).  None of them changes a result
+ * beyond rounding order; they select among equivalent schedules:
+ *   grad_variant[k] for layer-count bucket k (nr_bucket_lmax(k) layers):
+ *     NR_VARIANT_AUTO       the library's default for the bucket;
+ *     NR_VARIANT_STORE      forward sweep keeps states, phases and interface
+ *                           coefficients for the adjoint (only buckets of at
+ *                           most nr_store_max_layers(precision) layers);
+ *     NR_VARIANT_RECOMPUTE  the adjoint recomputes wavevectors and interface
+ *                           reciprocals (phases and roughness factors of the
+ *                           top levels come from an LDS cache).
+ *   xcd_run: consecutive work units of the cost-ordered list given to one of
+ *     the 8 XCDs (1..64; the default 8 keeps an item's units in one L2).
+ *   pack_tails: 1 packs the trailing partial point groups of several items
+ *     of equal depth into one wave (default); 0 gives each its own wave. */
+#define NR_NUM_BUCKETS 12
+#define NR_VARIANT_AUTO 0
+#define NR_VARIANT_STORE 1
+#define NR_VARIANT_RECOMPUTE 2
+typedef struct nr_plan_options {
+  int32_t grad_variant[NR_NUM_BUCKETS];
+  int32_t xcd_run;
+  int32_t pack_tails;
+} nr_plan_options;
+
+/* Fills *opts with the defaults (all NR_VARIANT_AUTO, xcd_run 8,
+ * pack_tails 1).  NR_EINVAL for NULL. */
+nr_status nr_plan_options_default(nr_plan_options* opts);
+
+/* Largest layer count L of bucket k (0 <= k < NR_NUM_BUCKETS): items with
+ * L <= nr_bucket_lmax(k) and L > nr_bucket_lmax(k-1) are evaluated at depth
+ * nr_bucket_lmax(k).  Returns -1 for k out of range. */
+int32_t nr_bucket_lmax(int32_t k);
+
+/* Deepest bucket (in layers) that NR_VARIANT_STORE supports at `precision`
+ * (NR_F64 or NR_F32); -1 for an unknown precision. */
+int32_t nr_store_max_layers(int32_t precision);
+
+/* nr_plan_create with options (NULL = defaults).  NR_EINVAL also for an
+ * option out of range or NR_VARIANT_STORE on a bucket deeper than
+ * nr_store_max_layers(precision). */
+nr_status nr_plan_create_ex(const nr_batch_desc* desc, const nr_plan_options* opts,
+                            nr_plan** plan_out);
+
 /* Releases a plan and its device memory.  NULL is accepted. */
 nr_status nr_plan_destroy(nr_plan* plan);
 

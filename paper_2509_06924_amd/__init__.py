@@ -20,7 +20,7 @@ from ._native import (NR_F32, NR_F64, NR_ITEM_BAD_ERR, NR_ITEM_BAD_Q,  # noqa: F
                       NR_ITEM_NONFINITE, NR_MAX_LAYERS, NR_OP_LOGLIK,
                       NR_OP_LOGLIK_GRAD, NR_OP_REFLECTIVITY, NativeError)
 
-__all__ = ["Plan", "Problem", "NRLogLik", "nr_reflectivity", "nr_loglik", "nr_loglik_grad",
+__all__ = ["Plan", "Problem", "plan_options", "bucket_lmax", "NRLogLik", "nr_reflectivity", "nr_loglik", "nr_loglik_grad",
            "pack_theta", "NativeError", "HmcState", "LeapfrogGraph", "tie_sum", "tie_map_to_csr"]
 
 
@@ -28,10 +28,41 @@ def _ptr(a):
     return ctypes.c_void_p(a.ctypes.data) if a is not None and a.size else None
 
 
+def bucket_lmax():
+    """Layer-count buckets of the library (deepest layer count of each)."""
+    L = _n.lib()
+    return [int(L.nr_bucket_lmax(k)) for k in range(_n.NR_NUM_BUCKETS)]
+
+
+def plan_options(options=None):
+    """nr_plan_options from None or a dict (see Plan)."""
+    o = _n.PlanOptions()
+    _n.check(_n.lib().nr_plan_options_default(ctypes.byref(o)))
+    if not options:
+        return o
+    gv = options.get("grad_variant")
+    if gv is not None:
+        if isinstance(gv, dict):
+            lm = bucket_lmax()
+            for key, v in gv.items():
+                o.grad_variant[lm.index(int(key))] = int(v)
+        else:
+            for k, v in enumerate(gv):
+                o.grad_variant[k] = int(v)
+    if "xcd_run" in options:
+        o.xcd_run = int(options["xcd_run"])
+    if "pack_tails" in options:
+        o.pack_tails = int(options["pack_tails"])
+    return o
+
+
 class Plan:
     """Owns an nr_plan built from host batch structure."""
 
-    def __init__(self, q_off, dq_over_q, dataset_of_item, row_off, precision=NR_F64):
+    def __init__(self, q_off, dq_over_q, dataset_of_item, row_off, precision=NR_F64,
+                 options=None):
+        """options: None (defaults) or a dict with any of grad_variant (list of
+        NR_NUM_BUCKETS ints or {bucket_lmax: variant}), xcd_run, pack_tails."""
         self.q_off = np.ascontiguousarray(q_off, np.int64)
         self.dq_over_q = np.ascontiguousarray(dq_over_q, np.float64)
         self.dataset_of_item = np.ascontiguousarray(dataset_of_item, np.int32)
@@ -43,7 +74,10 @@ class Plan:
         d.q_off = ctypes.c_void_p(self.q_off.ctypes.data)
         d.row_off = ctypes.c_void_p(self.row_off.ctypes.data)
         h = ctypes.c_void_p()
-        _n.check(_n.lib().nr_plan_create(ctypes.byref(d), ctypes.byref(h)))
+        self.precision = precision
+        self.options = plan_options(options)
+        _n.check(_n.lib().nr_plan_create_ex(ctypes.byref(d), ctypes.byref(self.options),
+                                            ctypes.byref(h)))
         self._h = h
         self.n_items = int(self.dataset_of_item.size)
         self.n_datasets = int(self.dq_over_q.size)
@@ -130,8 +164,9 @@ class Problem:
         self.out_off = plan.output_offsets()
 
     @classmethod
-    def from_batch(cls, batch, device="cuda", precision=NR_F64):
-        plan = Plan(batch.q_off, batch.dq_over_q, batch.dataset_of_item, batch.row_off, precision)
+    def from_batch(cls, batch, device="cuda", precision=NR_F64, options=None):
+        plan = Plan(batch.q_off, batch.dq_over_q, batch.dataset_of_item, batch.row_off, precision,
+                    options)
         return cls(plan, batch.Q, batch.Robs, batch.Rerr, batch.layers, batch.scale, batch.bkg,
                    device)
 

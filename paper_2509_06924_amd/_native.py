@@ -13,13 +13,16 @@ NR_OP_REFLECTIVITY, NR_OP_LOGLIK, NR_OP_LOGLIK_GRAD = 0, 1, 2
 NR_ITEM_NONFINITE, NR_ITEM_BAD_Q, NR_ITEM_BAD_ERR = 1, 2, 4
 NR_MAX_LAYERS = 40
 NR_SMEAR_NODES = 17
+NR_NUM_BUCKETS = 12
+NR_VARIANT_AUTO, NR_VARIANT_STORE, NR_VARIANT_RECOMPUTE = 0, 1, 2
 
 # every symbol include/nr.h declares
 EXPORTS = ("nr_version", "nr_status_string", "nr_plan_create", "nr_plan_destroy",
            "nr_workspace_size", "nr_output_offsets", "nr_reflectivity", "nr_loglik",
            "nr_loglik_grad", "nr_plan_set_timing_events", "nr_leapfrog",
            "nr_leapfrog_graph_create", "nr_graph_launch", "nr_graph_destroy",
-           "nr_vi_elbo_grad", "nr_tie_sum")
+           "nr_vi_elbo_grad", "nr_tie_sum", "nr_plan_options_default", "nr_bucket_lmax",
+           "nr_store_max_layers", "nr_plan_create_ex")
 
 
 class BatchDesc(ctypes.Structure):
@@ -31,6 +34,14 @@ class BatchDesc(ctypes.Structure):
         ("dataset_of_item", ctypes.c_void_p),
         ("row_off", ctypes.c_void_p),
         ("precision", ctypes.c_int32),
+    ]
+
+
+class PlanOptions(ctypes.Structure):
+    _fields_ = [
+        ("grad_variant", ctypes.c_int32 * NR_NUM_BUCKETS),
+        ("xcd_run", ctypes.c_int32),
+        ("pack_tails", ctypes.c_int32),
     ]
 
 
@@ -82,6 +93,15 @@ def lib():
         L.nr_status_string.argtypes = [ctypes.c_int32]
         L.nr_plan_create.restype = ctypes.c_int32
         L.nr_plan_create.argtypes = [ctypes.POINTER(BatchDesc), ctypes.POINTER(P)]
+        L.nr_plan_create_ex.restype = ctypes.c_int32
+        L.nr_plan_create_ex.argtypes = [ctypes.POINTER(BatchDesc), ctypes.POINTER(PlanOptions),
+                                        ctypes.POINTER(P)]
+        L.nr_plan_options_default.restype = ctypes.c_int32
+        L.nr_plan_options_default.argtypes = [ctypes.POINTER(PlanOptions)]
+        L.nr_bucket_lmax.restype = ctypes.c_int32
+        L.nr_bucket_lmax.argtypes = [ctypes.c_int32]
+        L.nr_store_max_layers.restype = ctypes.c_int32
+        L.nr_store_max_layers.argtypes = [ctypes.c_int32]
         L.nr_plan_destroy.restype = ctypes.c_int32
         L.nr_plan_destroy.argtypes = [P]
         L.nr_workspace_size.restype = ctypes.c_int32

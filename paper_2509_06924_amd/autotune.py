@@ -1,0 +1,157 @@
+"""Autotuner of the plan schedule for one batch structure.
+
+The library offers equivalent schedules of the same computation
+(`nr_plan_options` in include/nr.h): per layer-count bucket, the store or the
+recompute form of the gradient kernel; the length of the runs of work units
+given to one XCD; packing of the trailing partial point groups.  Which is
+fastest depends on the batch (depth mix, points per item, number of items)
+and the precision.  `tune` times `nr_loglik_grad` on the caller's own data
+under candidate schedules (coordinate search, CUDA events on the current
+stream, median of a few calls) and returns the fastest options; results are
+cached as JSON keyed by the batch's structure class, so the search runs once
+per class.
+
+    opts = autotune.tune(batch, precision=NR_F64)
+    prob = Problem.from_batch(batch, options=opts)
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import numpy as np
+
+from . import _native as _n
+from . import Plan, Problem, bucket_lmax
+
+XCD_RUNS = (1, 4, 8, 16, 32)
+
+
+def default_cache_path():
+    return os.environ.get("NR_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "paper_2509_06924_amd",
+                                       "autotune.json"))
+
+
+def structure_key(q_off, row_off, dataset_of_item, precision, device_name=""):
+    """Class of a batch structure: precision, the layer-count buckets present
+    (with their share of the work rounded to tenths), points per item and
+    number of items on a log2 scale, and the device."""
+    q_off = np.asarray(q_off, np.int64)
+    row_off = np.asarray(row_off, np.int64)
+    dsi = np.asarray(dataset_of_item, np.int64)
+    n = dsi.size
+    L = np.diff(row_off) - 2
+    nq = np.diff(q_off)[dsi] if n else np.zeros(0, np.int64)
+    lm = np.array(bucket_lmax())
+    b = np.searchsorted(lm, L) if n else np.zeros(0, np.int64)
+    work = (lm[b] + 1) * nq if n else np.zeros(0)
+    tot = float(work.sum()) or 1.0
+    shares = {int(lm[k]): round(float(work[b == k].sum()) / tot, 1) for k in np.unique(b)}
+    mean_nq = float(nq.mean()) if n else 0.0
+    return json.dumps({
+        "precision": int(precision),
+        "buckets": {str(k): v for k, v in sorted(shares.items()) if v > 0},
+        "log2_points_per_item": int(round(math.log2(mean_nq))) if mean_nq > 0 else 0,
+        "log2_items": int(round(math.log2(n))) if n > 0 else 0,
+        "device": device_name,
+        "library": int(_n.lib().nr_version()),
+    }, sort_keys=True)
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(path, table):
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _time_call(prob, out, reps):
+    import torch
+    stream = torch.cuda.current_stream()
+    prob.loglik_grad(out=out, stream=stream)
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        prob.loglik_grad(out=out, stream=stream)
+        b.record(stream)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def tune(batch, precision=_n.NR_F64, device="cuda", cache=None, reps=5, verbose=False,
+         use_cache=True):
+    """Fastest plan options for `batch` (an inputs.Batch or anything with the
+    same fields), as a dict for Plan / Problem.from_batch."""
+    import torch
+    dev = torch.device(device)
+    if dev.type == "cuda" and dev.index is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+    key = structure_key(batch.q_off, batch.row_off, batch.dataset_of_item, precision,
+                        torch.cuda.get_device_name(dev))
+    path = cache or default_cache_path()
+    table = _load(path) if use_cache else {}
+    if key in table:
+        return table[key]["options"]
+
+    base = Problem.from_batch(batch, device=dev, precision=precision)
+    out = base.loglik_grad()
+    # warm the device up (clocks, caches) before the first timed schedule
+    for _ in range(3):
+        _time_call(base, out, 1)
+
+    def problem(opts):
+        plan = Plan(batch.q_off, batch.dq_over_q, batch.dataset_of_item, batch.row_off,
+                    precision, opts)
+        return Problem(plan, base.q, base.r_obs, base.r_err, base.layers, base.scale, base.bkg,
+                       dev)
+
+    lm = bucket_lmax()
+    L = np.diff(np.asarray(batch.row_off)) - 2
+    used = sorted(set(int(lm[k]) for k in np.searchsorted(lm, L))) if L.size else []
+    smax = int(_n.lib().nr_store_max_layers(precision))
+    best = {"grad_variant": {}, "xcd_run": 8, "pack_tails": 1}
+    best_t = _time_call(problem(best), out, reps)
+    trials = [(dict(best), best_t)]
+
+    def consider(opts):
+        nonlocal best, best_t
+        t = _time_call(problem(opts), out, reps)
+        trials.append((opts, t))
+        if verbose:
+            print(f"autotune {opts}: {t:.3f} ms")
+        if t < best_t * 0.99:
+            best, best_t = opts, t
+
+    # buckets that have both forms default to the store form: try the other
+    for b in used:
+        if b <= smax:
+            gv = dict(best["grad_variant"])
+            gv[str(b)] = _n.NR_VARIANT_RECOMPUTE
+            consider({**best, "grad_variant": gv})
+    for run in XCD_RUNS:
+        if run != best["xcd_run"]:
+            consider({**best, "xcd_run": run})
+    consider({**best, "pack_tails": 1 - best["pack_tails"]})
+
+    record = {"options": best, "ms": best_t, "default_ms": trials[0][1],
+              "trials": len(trials)}
+    if use_cache:
+        table[key] = record
+        _save(path, table)
+    if verbose:
+        print(f"autotune best {best}: {best_t:.3f} ms (default {trials[0][1]:.3f} ms)")
+    return best

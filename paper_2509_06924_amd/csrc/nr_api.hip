@@ -91,6 +91,7 @@ void append_math_tables(std::vector<double>& v) {
 // partial groups of several items of equal depth, lane by lane.
 struct Launch {
   int bucket = 0;
+  bool store = false;  // gradient: store variant (else recompute)
   bool tail = false;
   int n_wu = 0;
   int32_t* item = nullptr;      // [n_wu]: the unit's item (first item for tails)
@@ -109,20 +110,19 @@ struct RecordLists {
 };
 
 // Workgroups are dispatched to the 8 XCDs round-robin (block b -> XCD b % 8)
-// and each XCD has its own L2.  Block b takes entry xcd_order(b, n) of the
-// cost-sorted unit list: within each chunk of 8 x kXcdRun blocks, one XCD
-// gets a run of kXcdRun consecutive entries (the units of one item are
+// and each XCD has its own L2.  Block b takes entry xcd_order(b, n, run) of
+// the cost-sorted unit list: within each chunk of 8 x run blocks, one XCD
+// gets a run of `run` consecutive entries (the units of one item are
 // consecutive), so an item's layer records are fetched into one L2, while
 // the chunks keep the longest-first order.  The last partial chunk maps to
 // itself.
 constexpr int kXcds = 8;
-constexpr size_t kXcdRun = 8;
-size_t xcd_order(size_t b, size_t n) {
-  const size_t chunk = kXcds * kXcdRun;
+size_t xcd_order(size_t b, size_t n, size_t run) {
+  const size_t chunk = kXcds * run;
   const size_t c0 = (b / chunk) * chunk;
   if (c0 + chunk > n) return b;
   const size_t r = b - c0;
-  return c0 + (r % kXcds) * kXcdRun + r / kXcds;
+  return c0 + (r % kXcds) * run + r / kXcds;
 }
 
 template <class T>
@@ -139,6 +139,8 @@ hipError_t upload(T** dst, const std::vector<T>& src) {
 struct nr_plan {
   int device = 0;
   int32_t n_datasets = 0, n_items = 0, precision = NR_F64;
+  nr_plan_options opts;
+  bool bucket_store[kNumBuckets];
   std::vector<int64_t> q_off, row_off, out_off;
   std::vector<int32_t> dataset_of_item;
   std::vector<double> dqq;
@@ -260,7 +262,7 @@ nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st, b
     a.tail_item = L.lane_item;
     a.tail_pt = L.lane_pt;
     a.tail_rec = L.lane_rec;
-    hipError_t e = grad ? launch_grad(p->precision, L.bucket, L.tail, a, L.n_wu, st)
+    hipError_t e = grad ? launch_grad(p->precision, L.bucket, L.store, L.tail, a, L.n_wu, st)
                         : launch_forward(p->precision, op, a, L.n_wu, st);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
   }
@@ -366,12 +368,53 @@ const char* nr_status_string(nr_status s) {
   }
 }
 
+nr_status nr_plan_options_default(nr_plan_options* o) {
+  if (!o) return NR_EINVAL;
+  for (int k = 0; k < NR_NUM_BUCKETS; ++k) o->grad_variant[k] = NR_VARIANT_AUTO;
+  o->xcd_run = 8;
+  o->pack_tails = 1;
+  return NR_OK;
+}
+
+int32_t nr_bucket_lmax(int32_t k) { return (k < 0 || k >= kNumBuckets) ? -1 : kBucketLmax[k]; }
+
+int32_t nr_store_max_layers(int32_t precision) {
+  if (precision != NR_F64 && precision != NR_F32) return -1;
+  return store_max_layers(precision);
+}
+
 nr_status nr_plan_create(const nr_batch_desc* d, nr_plan** out) {
+  return nr_plan_create_ex(d, nullptr, out);
+}
+
+nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts, nr_plan** out) {
   if (!out) return NR_EINVAL;
   *out = nullptr;
   nr_status st = validate_desc(d);
   if (st != NR_OK) return st;
+  nr_plan_options o;
+  nr_plan_options_default(&o);
+  if (opts) o = *opts;
+  if (o.xcd_run < 1 || o.xcd_run > 64 || (o.pack_tails != 0 && o.pack_tails != 1))
+    return NR_EINVAL;
+  bool bucket_store[kNumBuckets];
+  for (int k = 0; k < kNumBuckets; ++k) {
+    const int v = o.grad_variant[k];
+    const bool can_store = kBucketLmax[k] <= store_max_layers(d->precision);
+    if (v == NR_VARIANT_AUTO) {
+      bucket_store[k] = can_store;
+    } else if (v == NR_VARIANT_STORE) {
+      if (!can_store) return NR_EINVAL;
+      bucket_store[k] = true;
+    } else if (v == NR_VARIANT_RECOMPUTE) {
+      bucket_store[k] = false;
+    } else {
+      return NR_EINVAL;
+    }
+  }
   nr_plan* p = new nr_plan();
+  p->opts = o;
+  for (int k = 0; k < kNumBuckets; ++k) p->bucket_store[k] = bucket_store[k];
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return NR_EHIP;
@@ -487,13 +530,14 @@ nr_status nr_plan_create(const nr_batch_desc* d, nr_plan** out) {
       std::vector<int32_t> it(v.size()), p0(v.size());
       std::vector<int64_t> rc(v.size());
       for (size_t k = 0; k < v.size(); ++k) {
-        const size_t src = xcd_order(k, v.size());
+        const size_t src = xcd_order(k, v.size(), (size_t)p->opts.xcd_run);
         it[k] = v[src].item;
         p0[k] = v[src].p0;
         rc[k] = v[src].rec;
       }
       Launch L;
       L.bucket = bk;
+      L.store = p->bucket_store[bk];
       L.n_wu = (int)v.size();
       e = upload(&L.item, it);
       keep(L.item);
@@ -518,7 +562,7 @@ nr_status nr_plan_create(const nr_batch_desc* d, nr_plan** out) {
       std::vector<int> fill;  // lanes used per unit of this group
       std::vector<size_t> unit_base;
       for (const Tail& t : v) {
-        size_t u = 0;
+        size_t u = p->opts.pack_tails ? 0 : fill.size();
         while (u < fill.size() && fill[u] + t.count > kWuPoints) ++u;
         if (u == fill.size()) {
           fill.push_back(0);
@@ -548,6 +592,7 @@ nr_status nr_plan_create(const nr_batch_desc* d, nr_plan** out) {
           }
       Launch L;
       L.bucket = bk;
+      L.store = p->bucket_store[bk];
       L.tail = true;
       L.n_wu = (int)b_item[bk].size();
       e = upload(&L.item, b_item[bk]);

@@ -36,6 +36,7 @@ constexpr int kOpLoglikGrad = NR_OP_LOGLIK_GRAD;
 #define NR_BUCKETS(X) X(1) X(2) X(4) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40)
 constexpr int kBucketLmax[] = {1, 2, 4, 6, 8, 10, 12, 16, 20, 24, 32, 40};
 constexpr int kNumBuckets = sizeof(kBucketLmax) / sizeof(int);
+static_assert(kNumBuckets == NR_NUM_BUCKETS, "bucket table and ABI disagree");
 
 inline int bucket_of(int N) {
   for (int b = 0; b < kNumBuckets; ++b)
@@ -95,10 +96,15 @@ hipError_t launch_item_consts(const int64_t* row_off, const double* layers, doub
                               float* recf, int n_items, hipStream_t st);
 // precision: NR_F64 or NR_F32
 hipError_t launch_forward(int precision, int op, const KernelArgs& a, int n_wu, hipStream_t st);
-hipError_t launch_grad(int precision, int bucket, bool tail, const KernelArgs& a, int n_wu,
-                       hipStream_t st);
+// store: the store variant (only for buckets within store_max_layers)
+hipError_t launch_grad(int precision, int bucket, bool store, bool tail, const KernelArgs& a,
+                       int n_wu, hipStream_t st);
 hipError_t launch_forward_f32(int op, const KernelArgs& a, int n_wu, hipStream_t st);
-hipError_t launch_grad_f32(int bucket, bool tail, const KernelArgs& a, int n_wu, hipStream_t st);
+hipError_t launch_grad_f32(int bucket, bool store, bool tail, const KernelArgs& a, int n_wu,
+                           hipStream_t st);
+inline int store_max_layers(int precision) {
+  return precision == NR_F32 ? kStoreMaxLayersF32 : kStoreMaxLayers;
+}
 hipError_t launch_reduce(int op, const ReduceArgs& a, hipStream_t st);
 
 hipError_t launch_kick(int64_t n_row_entries, int64_t n_inst, double* mom_rows,

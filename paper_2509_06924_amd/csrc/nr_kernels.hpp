@@ -832,20 +832,31 @@ hipError_t launch_forward_p(int op, const KernelArgs& a, int n_wu, hipStream_t s
 }
 
 template <class P>
-hipError_t launch_grad_p(int bucket, bool tail, const KernelArgs& a, int n_wu, hipStream_t st) {
+hipError_t launch_grad_p(int bucket, bool store, bool tail, const KernelArgs& a, int n_wu,
+                         hipStream_t st) {
   if (n_wu <= 0) return hipSuccess;
   switch (kBucketLmax[bucket]) {
+#define NR_LAUNCH(LM, S)                                                                      \
+  if (tail)                                                                                   \
+    hipLaunchKernelGGL((k_loglik_grad<P, LM, S, true>), dim3(n_wu), dim3(64), 0, st, a);       \
+  else                                                                                        \
+    hipLaunchKernelGGL((k_loglik_grad<P, LM, S, false>), dim3(n_wu), dim3(64), 0, st, a);
 #define NR_CASE(LM)                                                                           \
   case LM:                                                                                    \
-    if (tail)                                                                                 \
-      hipLaunchKernelGGL((k_loglik_grad<P, LM, (LM <= P::kStoreMax), true>), dim3(n_wu),      \
-                         dim3(64), 0, st, a);                                                 \
-    else                                                                                      \
-      hipLaunchKernelGGL((k_loglik_grad<P, LM, (LM <= P::kStoreMax), false>), dim3(n_wu),     \
-                         dim3(64), 0, st, a);                                                 \
+    if constexpr (LM <= P::kStoreMax) {                                                       \
+      if (store) {                                                                            \
+        NR_LAUNCH(LM, true)                                                                   \
+      } else {                                                                                \
+        NR_LAUNCH(LM, false)                                                                  \
+      }                                                                                       \
+    } else {                                                                                  \
+      if (store) return hipErrorInvalidValue;                                                 \
+      NR_LAUNCH(LM, false)                                                                    \
+    }                                                                                         \
     return hipGetLastError();
     NR_BUCKETS(NR_CASE)
 #undef NR_CASE
+#undef NR_LAUNCH
     default:
       return hipErrorInvalidValue;
   }

@@ -8,8 +8,9 @@ hipError_t launch_forward_f32(int op, const KernelArgs& a, int n_wu, hipStream_t
   return launch_forward_p<F32>(op, a, n_wu, st);
 }
 
-hipError_t launch_grad_f32(int bucket, bool tail, const KernelArgs& a, int n_wu, hipStream_t st) {
-  return launch_grad_p<F32>(bucket, tail, a, n_wu, st);
+hipError_t launch_grad_f32(int bucket, bool store, bool tail, const KernelArgs& a, int n_wu,
+                           hipStream_t st) {
+  return launch_grad_p<F32>(bucket, store, tail, a, n_wu, st);
 }
 
 }  // namespace nr

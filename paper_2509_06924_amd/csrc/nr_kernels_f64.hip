@@ -117,10 +117,10 @@ hipError_t launch_forward(int precision, int op, const KernelArgs& a, int n_wu, 
                              : launch_forward_p<F64>(op, a, n_wu, st);
 }
 
-hipError_t launch_grad(int precision, int bucket, bool tail, const KernelArgs& a, int n_wu,
-                       hipStream_t st) {
-  return precision == NR_F32 ? launch_grad_f32(bucket, tail, a, n_wu, st)
-                             : launch_grad_p<F64>(bucket, tail, a, n_wu, st);
+hipError_t launch_grad(int precision, int bucket, bool store, bool tail, const KernelArgs& a,
+                       int n_wu, hipStream_t st) {
+  return precision == NR_F32 ? launch_grad_f32(bucket, store, tail, a, n_wu, st)
+                             : launch_grad_p<F64>(bucket, store, tail, a, n_wu, st);
 }
 
 hipError_t launch_reduce(int op, const ReduceArgs& a, hipStream_t st) {

@@ -107,3 +107,66 @@ def test_paper_parameter_dict_packs_to_rows():
     assert np.allclose(rows[:, 1], np.array(g["theta"]["SLD"]) * 1e-6)
     assert np.array_equal(rows[1:, 3], g["theta"]["rough"])
     assert rows[0, 0] == 0 and rows[-1, 0] == 0 and rows[0, 3] == 0
+
+
+def test_bucket_table_and_store_limits():
+    n, L = _lib()
+    lm = [L.nr_bucket_lmax(k) for k in range(n.NR_NUM_BUCKETS)]
+    assert lm == sorted(lm) and lm[-1] == n.NR_MAX_LAYERS and lm[0] >= 1
+    assert L.nr_bucket_lmax(-1) == -1 and L.nr_bucket_lmax(n.NR_NUM_BUCKETS) == -1
+    for prec in (n.NR_F64, n.NR_F32):
+        assert L.nr_store_max_layers(prec) in lm
+    assert L.nr_store_max_layers(7) == -1
+
+
+def test_plan_options_defaults_and_dict():
+    n, L = _lib()
+    from paper_2509_06924_amd import plan_options
+    o = plan_options()
+    assert list(o.grad_variant) == [n.NR_VARIANT_AUTO] * n.NR_NUM_BUCKETS
+    assert o.xcd_run == 8 and o.pack_tails == 1
+    o = plan_options({"grad_variant": {"10": n.NR_VARIANT_RECOMPUTE}, "xcd_run": 4,
+                      "pack_tails": 0})
+    k10 = [L.nr_bucket_lmax(k) for k in range(n.NR_NUM_BUCKETS)].index(10)
+    assert o.grad_variant[k10] == n.NR_VARIANT_RECOMPUTE and o.xcd_run == 4 and o.pack_tails == 0
+
+
+@pytest.mark.parametrize("case", ["xcd_zero", "xcd_big", "pack_two", "variant_unknown",
+                                  "store_too_deep_f64", "store_too_deep_f32"])
+def test_invalid_plan_options_rejected(case):
+    n, L = _lib()
+    from paper_2509_06924_amd import plan_options
+    o = plan_options()
+    prec = n.NR_F64
+    deep = n.NR_NUM_BUCKETS - 1
+    if case == "xcd_zero":
+        o.xcd_run = 0
+    elif case == "xcd_big":
+        o.xcd_run = 65
+    elif case == "pack_two":
+        o.pack_tails = 2
+    elif case == "variant_unknown":
+        o.grad_variant[0] = 9
+    elif case == "store_too_deep_f64":
+        o.grad_variant[deep] = n.NR_VARIANT_STORE
+    else:
+        prec = n.NR_F32
+        o.grad_variant[deep] = n.NR_VARIANT_STORE
+    d, keep = _desc(n, [0, 10, 20], [0.05, 0.0], [0, 1], [0, 4, 7], prec)
+    h = ctypes.c_void_p()
+    assert L.nr_plan_create_ex(ctypes.byref(d), ctypes.byref(o), ctypes.byref(h)) == n.NR_EINVAL
+    assert not h.value
+
+
+def test_autotune_structure_key_classes():
+    """Batches of the same shape class share a key; depth mix, size class and
+    precision separate them."""
+    _lib()
+    from paper_2509_06924_amd import autotune, inputs
+    a = inputs.c2_batched(n_items=256)
+    b = inputs.c2_batched(n_items=256, seed_offset=9)
+    c = inputs.c2_batched(n_items=256, L=20)
+    k = lambda x, p=0: autotune.structure_key(x.q_off, x.row_off, x.dataset_of_item, p, "dev")
+    assert k(a) == k(b)
+    assert k(a) != k(c) and k(a) != k(a, 1)
+    assert k(a) != k(inputs.c2_batched(n_items=1024))
