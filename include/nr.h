@@ -129,7 +129,9 @@ nr_status nr_plan_create(const nr_batch_desc* desc, nr_plan** plan_out);
 /* Plan tuning options (nr_plan_create_ex).  None of them changes a result
  * beyond rounding order; they select among equivalent schedules:
  *   grad_variant[k] for layer-count bucket k (nr_bucket_lmax(k) layers):
- *     NR_VARIANT_AUTO       the library's default for the bucket;
+ *     NR_VARIANT_AUTO       the library's default for the bucket: the store
+ *                           form up to 4 layers in NR_F64 and 8 in NR_F32,
+ *                           the recompute form deeper (the faster on MI355X);
  *     NR_VARIANT_STORE      forward sweep keeps states, phases and interface
  *                           coefficients for the adjoint (only buckets of at
  *                           most nr_store_max_layers(precision) layers);

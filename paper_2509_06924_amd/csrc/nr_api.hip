@@ -402,7 +402,7 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
     const int v = o.grad_variant[k];
     const bool can_store = kBucketLmax[k] <= store_max_layers(d->precision);
     if (v == NR_VARIANT_AUTO) {
-      bucket_store[k] = can_store;
+      bucket_store[k] = kBucketLmax[k] <= default_store_layers(d->precision);
     } else if (v == NR_VARIANT_STORE) {
       if (!can_store) return NR_EINVAL;
       bucket_store[k] = true;

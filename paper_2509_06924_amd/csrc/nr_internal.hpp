@@ -105,6 +105,12 @@ hipError_t launch_grad_f32(int bucket, bool store, bool tail, const KernelArgs& 
 inline int store_max_layers(int precision) {
   return precision == NR_F32 ? kStoreMaxLayersF32 : kStoreMaxLayers;
 }
+// Deepest bucket whose default (NR_VARIANT_AUTO) is the store variant.
+// Measured on MI355X at 4096 items x 400 points: FP64 store beats the
+// recompute form (with its LDS cache of phases and roughness factors, two
+// waves per SIMD) up to 4 layers (0.71 vs 0.60 of peak) and loses from 6 on
+// (10 layers: 0.56 vs 0.60); FP32 store wins up to 8 layers.
+inline int default_store_layers(int precision) { return precision == NR_F32 ? 8 : 4; }
 hipError_t launch_reduce(int op, const ReduceArgs& a, hipStream_t st);
 
 hipError_t launch_kick(int64_t n_row_entries, int64_t n_inst, double* mom_rows,

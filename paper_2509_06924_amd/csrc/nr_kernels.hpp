@@ -59,7 +59,11 @@ struct F64 {
   // recompute variant: levels whose phase and Nevot-Croce factor are kept in
   // LDS (2 KB per level per wave; ~36 KB of the 40 KB a wave may use at one
   // wave per SIMD)
-  static constexpr int ef_levels(int lmax) { return lmax + 1 < 17 ? lmax + 1 : 17; }
+  // (up to 10 layers the kernel fits two waves per SIMD in registers, so its
+  // LDS is held to 20 KB: 8 levels)
+  static constexpr int ef_levels(int lmax) {
+    return lmax <= 10 ? (lmax + 1 < 8 ? lmax + 1 : 8) : (lmax + 1 < 17 ? lmax + 1 : 17);
+  }
 };
 struct F32 {
   using real = float;
