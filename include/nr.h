@@ -83,6 +83,10 @@ typedef int32_t nr_status;
 #define NR_ITEM_NONFINITE 1u /* a non-finite R, logL or gradient value */
 #define NR_ITEM_BAD_Q 2u     /* a data point or a quadrature node q <= 0 */
 #define NR_ITEM_BAD_ERR 4u   /* an error bar e_i <= 0 or non-finite */
+#define NR_ITEM_EDGE_SINGULAR 8u /* gradient calls: w_j = kz0^2 - 4 pi (rho_j - rho_0)
+                                  * - i 4 pi |rho_im,j| is exactly 0 at some node, where
+                                  * dkz/dw is infinite; the item's gradient is finite
+                                  * but not meaningful there (logL is unaffected) */
 
 typedef struct nr_plan nr_plan;
 
@@ -203,6 +207,19 @@ nr_status nr_loglik(const nr_plan* plan, const nr_values* v, double* logL,
 nr_status nr_loglik_grad(const nr_plan* plan, const nr_values* v, double* logL,
                          double* g_rows, double* g_inst, void* workspace,
                          size_t workspace_bytes, void* stream);
+
+/* Vector-Jacobian product of R_hat (the autograd of nr_reflectivity): for
+ * per-point seeds v (device, packed like R_hat, see nr_output_offsets) writes
+ * per item b
+ *   dot[b]        = sum_i v_i R_hat_i,
+ *   g_rows        = sum_i v_i dR_hat_i / d(row entries)  (packed like layers),
+ *   g_inst[2b]    = sum_i v_i R_sm_i  (d/dscale),   g_inst[2b+1] = sum_i v_i.
+ * The same forward model as nr_reflectivity (Sec. 2.1, Sec. 3); r_obs and
+ * r_err are not read.  Uses the NR_OP_LOGLIK_GRAD workspace.  Status bits as
+ * for nr_loglik_grad (NONFINITE, BAD_Q, EDGE_SINGULAR). */
+nr_status nr_reflectivity_vjp(const nr_plan* plan, const nr_values* values, const double* seed,
+                              double* dot, double* g_rows, double* g_inst, void* workspace,
+                              size_t workspace_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Integrators and co-fit ties around the gradient.

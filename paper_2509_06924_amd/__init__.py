@@ -17,11 +17,13 @@ import numpy as np
 
 from . import _native as _n
 from ._native import (NR_F32, NR_F64, NR_ITEM_BAD_ERR, NR_ITEM_BAD_Q,  # noqa: F401
+                      NR_ITEM_EDGE_SINGULAR,
                       NR_ITEM_NONFINITE, NR_MAX_LAYERS, NR_OP_LOGLIK,
                       NR_OP_LOGLIK_GRAD, NR_OP_REFLECTIVITY, NativeError)
 
-__all__ = ["Plan", "Problem", "plan_options", "bucket_lmax", "NRLogLik", "nr_reflectivity", "nr_loglik", "nr_loglik_grad",
-           "pack_theta", "NativeError", "HmcState", "LeapfrogGraph", "tie_sum", "tie_map_to_csr"]
+__all__ = ["Plan", "Problem", "plan_options", "bucket_lmax", "NRLogLik", "NRReflectivity",
+           "nr_reflectivity", "nr_loglik", "nr_loglik_grad", "pack_theta", "NativeError",
+           "HmcState", "LeapfrogGraph", "tie_sum", "tie_map_to_csr"]
 
 
 def _ptr(a):
@@ -216,6 +218,27 @@ class Problem:
         return logL, g_rows, g_inst
 
 
+def _reflectivity_vjp(self, seed, layers=None, scale=None, bkg=None, stream=None):
+    """Vector-Jacobian product of R_hat for per-point seeds (packed like
+    R_hat): returns (dot = sum_i seed_i R_hat_i per item, g_rows, g_inst)."""
+    import torch
+    seed_t = torch.as_tensor(seed, dtype=torch.float64, device=self.device).reshape(-1)
+    seed_t = seed_t.contiguous()
+    if seed_t.numel() != int(self.out_off[-1]):
+        raise ValueError("seed must hold one value per data point of every item")
+    dot = torch.empty(self.plan.n_items, dtype=torch.float64, device=self.device)
+    g_rows = torch.empty_like(self.layers)
+    g_inst = torch.empty(self.plan.n_items, 2, dtype=torch.float64, device=self.device)
+    ws = self.workspace(NR_OP_LOGLIK_GRAD)
+    _n.check(_n.lib().nr_reflectivity_vjp(
+        self.plan.handle, ctypes.byref(self.values(layers, scale, bkg)), _dp(seed_t), _dp(dot),
+        _dp(g_rows), _dp(g_inst), _dp(ws), ws.numel() * 8, _stream(stream)))
+    return dot, g_rows, g_inst
+
+
+Problem.reflectivity_vjp = _reflectivity_vjp
+
+
 class HmcState:
     """Device tensors of an HMC state: positions (copies of the problem's
     parameters), momenta, optional inverse masses, and logL/gradient at the
@@ -366,19 +389,41 @@ def _make_autograd():
             go_rows = grad_out[ctx.row_item].unsqueeze(1)
             return g_rows * go_rows, g_inst[:, 0] * grad_out, g_inst[:, 1] * grad_out, None
 
-    return NRLogLik
+    class NRReflectivity(torch.autograd.Function):
+        """R_hat (packed item-major, nr_output_offsets) as a differentiable
+        function of (layers, scale, bkg); backward is nr_reflectivity_vjp."""
+
+        @staticmethod
+        def forward(ctx, layers, scale, bkg, problem):
+            args = [t.detach().contiguous() for t in (layers, scale, bkg)]
+            ctx.problem = problem
+            ctx.save_for_backward(*args)
+            return problem.reflectivity(*args)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            layers, scale, bkg = ctx.saved_tensors
+            _, g_rows, g_inst = ctx.problem.reflectivity_vjp(grad_out.contiguous(), layers,
+                                                              scale, bkg)
+            return g_rows, g_inst[:, 0], g_inst[:, 1], None
+
+    return NRLogLik, NRReflectivity
 
 
 class _LazyAutograd:
     _cls = None
 
+    def __init__(self, which):
+        self._which = which
+
     def __getattr__(self, name):
         if _LazyAutograd._cls is None:
             _LazyAutograd._cls = _make_autograd()
-        return getattr(_LazyAutograd._cls, name)
+        return getattr(_LazyAutograd._cls[self._which], name)
 
 
-NRLogLik = _LazyAutograd()
+NRLogLik = _LazyAutograd(0)
+NRReflectivity = _LazyAutograd(1)
 
 
 def _row_item(problem):

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(_PKG, "libnr.so")
 NR_OK, NR_EINVAL, NR_EWORKSPACE, NR_EHIP, NR_ENOMEM = 0, 1, 2, 3, 4
 NR_F64, NR_F32 = 0, 1
 NR_OP_REFLECTIVITY, NR_OP_LOGLIK, NR_OP_LOGLIK_GRAD = 0, 1, 2
-NR_ITEM_NONFINITE, NR_ITEM_BAD_Q, NR_ITEM_BAD_ERR = 1, 2, 4
+NR_ITEM_NONFINITE, NR_ITEM_BAD_Q, NR_ITEM_BAD_ERR, NR_ITEM_EDGE_SINGULAR = 1, 2, 4, 8
 NR_MAX_LAYERS = 40
 NR_SMEAR_NODES = 17
 NR_NUM_BUCKETS = 12
@@ -22,7 +22,7 @@ EXPORTS = ("nr_version", "nr_status_string", "nr_plan_create", "nr_plan_destroy"
            "nr_loglik_grad", "nr_plan_set_timing_events", "nr_leapfrog",
            "nr_leapfrog_graph_create", "nr_graph_launch", "nr_graph_destroy",
            "nr_vi_elbo_grad", "nr_tie_sum", "nr_plan_options_default", "nr_bucket_lmax",
-           "nr_store_max_layers", "nr_plan_create_ex")
+           "nr_store_max_layers", "nr_plan_create_ex", "nr_reflectivity_vjp")
 
 
 class BatchDesc(ctypes.Structure):
@@ -114,6 +114,9 @@ def lib():
         L.nr_loglik.argtypes = [P, ctypes.POINTER(Values), P, P, ctypes.c_size_t, P]
         L.nr_loglik_grad.restype = ctypes.c_int32
         L.nr_loglik_grad.argtypes = [P, ctypes.POINTER(Values), P, P, P, P, ctypes.c_size_t, P]
+        L.nr_reflectivity_vjp.restype = ctypes.c_int32
+        L.nr_reflectivity_vjp.argtypes = [P, ctypes.POINTER(Values), P, P, P, P, P,
+                                          ctypes.c_size_t, P]
         L.nr_plan_set_timing_events.restype = ctypes.c_int32
         L.nr_plan_set_timing_events.argtypes = [P, P, P]
         L.nr_leapfrog.restype = ctypes.c_int32

@@ -273,10 +273,13 @@ nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st, b
   return NR_OK;
 }
 
-// Enqueues the whole logL + gradient evaluation (validated arguments).
+// Enqueues the whole logL + gradient evaluation (validated arguments); with
+// seed set, the vector-Jacobian product of R_hat instead.
 nr_status enqueue_grad(const nr_plan* p, const nr_values* v, double* logL, double* g_rows,
-                       double* g_inst, void* ws, hipStream_t s, bool events) {
+                       double* g_inst, void* ws, hipStream_t s, bool events,
+                       const double* seed = nullptr) {
   KernelArgs a = base_args(p, v);
+  a.seed = seed;
   a.consts = static_cast<double*>(ws);
   a.constsf = consts_floats(p, a.consts);
   a.rec = static_cast<double*>(ws) + consts_doubles(p);
@@ -773,6 +776,19 @@ nr_status nr_loglik(const nr_plan* p, const nr_values* v, double* logL, void* ws
   r.logL = logL;
   hipError_t e = launch_reduce(kOpLoglik, r, s);
   return e == hipSuccess ? NR_OK : hip_fail(e, "reduce launch");
+}
+
+nr_status nr_reflectivity_vjp(const nr_plan* p, const nr_values* v, const double* seed,
+                              double* dot, double* g_rows, double* g_inst, void* ws,
+                              size_t ws_bytes, void* stream) {
+  nr_status st = check_call(p, v, false);
+  if (st != NR_OK) return st;
+  if (p->n_items == 0) return NR_OK;
+  if (!dot || !g_rows || !g_inst) return NR_EINVAL;
+  if (p->out_off.back() > 0 && !seed) return NR_EINVAL;
+  const size_t need = sizeof(double) * op_doubles(p, NR_OP_LOGLIK_GRAD);
+  if (need > 0 && (!ws || ws_bytes < need)) return NR_EWORKSPACE;
+  return enqueue_grad(p, v, dot, g_rows, g_inst, ws, (hipStream_t)stream, true, seed);
 }
 
 nr_status nr_loglik_grad(const nr_plan* p, const nr_values* v, double* logL, double* g_rows,

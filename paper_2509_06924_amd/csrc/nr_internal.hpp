@@ -25,6 +25,7 @@ constexpr int kRecFloats = 8;
 constexpr uint32_t kItemNonfinite = NR_ITEM_NONFINITE;
 constexpr uint32_t kItemBadQ = NR_ITEM_BAD_Q;
 constexpr uint32_t kItemBadErr = NR_ITEM_BAD_ERR;
+constexpr uint32_t kItemEdgeSingular = NR_ITEM_EDGE_SINGULAR;
 
 constexpr int kOpReflectivity = NR_OP_REFLECTIVITY;
 constexpr int kOpLoglik = NR_OP_LOGLIK;
@@ -69,6 +70,9 @@ struct KernelArgs {
   int32_t* item_status;
   // outputs
   double* out;     // nr_reflectivity
+  // nr_reflectivity_vjp: per-point seeds (packed like R_hat); when set, the
+  // gradient kernel differentiates sum_i seed_i R_hat_i instead of logL
+  const double* seed;
   double* rec;     // workspace records
   const double* consts;  // workspace: per-item layer records (6 doubles per row)
   const float* constsf;  // workspace: their float copies (8 floats per row)

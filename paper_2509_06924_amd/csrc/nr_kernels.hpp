@@ -198,6 +198,18 @@ __device__ __forceinline__ RootT<typename P::real> medium_root(const Layers<P>& 
   return kz_root(static_cast<Re>(kz_real_part(kz0sq, L.A(m))), -L.B(m));
 }
 
+// The same, recording whether w_m = 0 exactly (x = 0 and no absorption): the
+// root's derivative 1/(2 kz) is infinite there.
+template <class P>
+__device__ __forceinline__ RootT<typename P::real> medium_root(const Layers<P>& L, double kz0sq,
+                                                               int m, bool& edge) {
+  using Re = typename P::real;
+  const double x = kz_real_part(kz0sq, L.A(m));
+  const Re b = L.B(m);
+  edge |= (x == 0.0) & (b == Re(0));
+  return kz_root(static_cast<Re>(x), -b);
+}
+
 template <class P>
 __device__ __forceinline__ cx<typename P::real> fronting_kz(double q) {
   using Re = typename P::real;
@@ -499,7 +511,7 @@ template <class P, int LMAX>
 __device__ __forceinline__ double node_grad_store(const MathTables& T, const Layers<P>& L,
                                                   GradTape<typename P::real, LMAX>& tp,
                                                   Accum<LMAX>& acc, int lane, double q,
-                                                  double wk) {
+                                                  double wk, bool& edge) {
   using Re = typename P::real;
   using Cx = cx<Re>;
   const double kz0sq = kz0_squared(q);
@@ -512,7 +524,7 @@ __device__ __forceinline__ double node_grad_store(const MathTables& T, const Lay
   Cx krp[kSlim ? 1 : LMAX + 1], kkk[kSlim ? 1 : LMAX + 1];
   Cx Pv = mk(Re(1), Re(0)), Qv = mk(Re(0), Re(0));
   {
-    const RootT<Re> rt = medium_root(L, kz0sq, LMAX + 1);
+    const RootT<Re> rt = medium_root(L, kz0sq, LMAX + 1, edge);
     kz[LMAX + 1] = rt.kz;
     ia[LMAX + 1] = rt.inv_abs2;
   }
@@ -524,7 +536,7 @@ __device__ __forceinline__ double node_grad_store(const MathTables& T, const Lay
       kz[0] = fronting_kz<P>(q);
       ia[0] = Re(0);
     } else {
-      const RootT<Re> rt = medium_root(L, kz0sq, jj);
+      const RootT<Re> rt = medium_root(L, kz0sq, jj, edge);
       kz[jj] = rt.kz;
       ia[jj] = rt.inv_abs2;
     }
@@ -603,17 +615,17 @@ template <class P, int LMAX, int KS>
 __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const Layers<P>& L,
                                                       EfCache<typename P::real, KS>& ef,
                                                       Accum<LMAX>& acc, int lane, double q,
-                                                      double wk) {
+                                                      double wk, bool& edge) {
   using Re = typename P::real;
   using Cx = cx<Re>;
   const double kz0sq = kz0_squared(q);
   const Cx kz0 = fronting_kz<P>(q);
   Cx tapeP[LMAX + 1], tapeQ[LMAX + 1];
-  Cx kzn = medium_root(L, kz0sq, LMAX + 1).kz;
+  Cx kzn = medium_root(L, kz0sq, LMAX + 1, edge).kz;
   Cx Pv = mk(Re(1), Re(0)), Qv = mk(Re(0), Re(0));
 #pragma unroll
   for (int jj = LMAX; jj >= 0; --jj) {
-    const Cx kzc = (jj == 0) ? kz0 : medium_root(L, kz0sq, jj).kz;
+    const Cx kzc = (jj == 0) ? kz0 : medium_root(L, kz0sq, jj, edge).kz;
     tapeP[jj] = Pv;
     tapeQ[jj] = Qv;
     const Iface<Re> it = interface_coeffs(T, kzc, kzn, L.Nr(jj), L.Ni(jj), L.C(jj));
@@ -711,6 +723,7 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX)) void k_loglik_grad(KernelAr
 
   double Rsm = 0.0;
   bool badq = !(u.Q > 0.0);
+  bool edge = false;
   for (int k = 0; k < K; ++k) {
     const double q = (K == 1) ? u.Q : smear_node(u.Q, u.dqq, ld(s.t[k]));
     badq |= !(q > 0.0);
@@ -718,9 +731,9 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX)) void k_loglik_grad(KernelAr
     const Layers<P> L = item_layers<P>(a, u.roff, N, k);
     double R;
     if constexpr (STORE)
-      R = node_grad_store<P, LMAX>(s.tab, L, tape, acc, lane, q, wk);
+      R = node_grad_store<P, LMAX>(s.tab, L, tape, acc, lane, q, wk, edge);
     else
-      R = node_grad_recompute<P, LMAX, KS>(s.tab, L, efc, acc, lane, q, wk);
+      R = node_grad_recompute<P, LMAX, KS>(s.tab, L, efc, acc, lane, q, wk, edge);
     Rsm += wk * R;
   }
   // the item was evaluated at depth LMAX: the copies of the backing below it
@@ -741,12 +754,22 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX)) void k_loglik_grad(KernelAr
   if (u.active) {
     const double sc = a.scale[u.item];
     const double Rhat = sc * Rsm + a.bkg[u.item];
-    const double e = a.r_err[u.qoff + u.i];
-    ll = point_loglik(Rhat, a.r_obs[u.qoff + u.i], e, badq, bits);
-    const double ghat = -(Rhat - a.r_obs[u.qoff + u.i]) / (e * e);
+    double ghat;
+    if (a.seed != nullptr) {
+      // vector-Jacobian product of R_hat: the seed replaces dlogL/dR_hat
+      ghat = a.seed[a.out_off[u.item] + u.i];
+      ll = badq ? __builtin_nan("") : ghat * Rhat;
+      if (badq) bits |= kItemBadQ;
+      if (!isfinite(ll)) bits |= kItemNonfinite;
+    } else {
+      const double e = a.r_err[u.qoff + u.i];
+      ll = point_loglik(Rhat, a.r_obs[u.qoff + u.i], e, badq, bits);
+      ghat = -(Rhat - a.r_obs[u.qoff + u.i]) / (e * e);
+    }
     gsc = ghat * Rsm;
     gbk = ghat;
     fac = ghat * sc;
+    if (edge) bits |= kItemEdgeSingular;
   }
   flag(a.item_status, u.item, bits);
 
