@@ -146,7 +146,7 @@ nr_status nr_plan_create(const nr_batch_desc* desc, nr_plan** plan_out);
  *     the 8 XCDs (1..64; the default 8 keeps an item's units in one L2).
  *   pack_tails: 1 packs the trailing partial point groups of several items
  *     of equal depth into one wave (default); 0 gives each its own wave. */
-#define NR_NUM_BUCKETS 12
+#define NR_NUM_BUCKETS 16
 #define NR_VARIANT_AUTO 0
 #define NR_VARIANT_STORE 1
 #define NR_VARIANT_RECOMPUTE 2

@@ -13,7 +13,7 @@ NR_OP_REFLECTIVITY, NR_OP_LOGLIK, NR_OP_LOGLIK_GRAD = 0, 1, 2
 NR_ITEM_NONFINITE, NR_ITEM_BAD_Q, NR_ITEM_BAD_ERR, NR_ITEM_EDGE_SINGULAR = 1, 2, 4, 8
 NR_MAX_LAYERS = 40
 NR_SMEAR_NODES = 17
-NR_NUM_BUCKETS = 12
+NR_NUM_BUCKETS = 16
 NR_VARIANT_AUTO, NR_VARIANT_STORE, NR_VARIANT_RECOMPUTE = 0, 1, 2
 
 # every symbol include/nr.h declares

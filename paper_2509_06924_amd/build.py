@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import os
+import re
 import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -14,6 +15,17 @@ LIB = os.path.join(PKG, "libnr.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
 SOURCES = ["nr_api.hip", "nr_kernels_f64.hip", "nr_kernels_f32.hip", "nr_integrators.hip"]
+# compiled once per (precision, deep bucket); the bucket list is read from
+# the NR_BUCKETS_DEEP macro so it cannot drift from the C++ side
+BUCKET_SOURCE = "nr_kernels_bucket.hip"
+
+
+def deep_buckets():
+    text = open(os.path.join(CSRC, "nr_internal.hpp")).read()
+    m = re.search(r"#define NR_BUCKETS_DEEP\(X\)((?:\s*X\(\d+\))+)", text)
+    if not m:
+        raise RuntimeError("NR_BUCKETS_DEEP not found in nr_internal.hpp")
+    return [int(v) for v in re.findall(r"X\((\d+)\)", m.group(1))]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -24,9 +36,10 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(job) -> str:
+    src, defines, tag = job
+    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + tag + ".o")
+    cmd = [HIPCC, *FLAGS, *defines, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
@@ -36,8 +49,16 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    jobs = [(src, [], "") for src in SOURCES]
+    # the deepest (slowest) buckets first
+    for lm in sorted(deep_buckets(), reverse=True):
+        for prec in ("F64", "F32"):
+            jobs.append((BUCKET_SOURCE, [f"-DNR_PREC={prec}", f"-DNR_BUCKET_LMAX={lm}"],
+                         f"_{prec}_{lm}"))
+    jobs.sort(key=lambda j: 0 if j[0] == BUCKET_SOURCE else 1)
+    workers = max(1, min(len(jobs), os.cpu_count() or 4))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(_compile, jobs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -34,8 +34,12 @@ constexpr int kOpLoglikGrad = NR_OP_LOGLIK_GRAD;
 // Layer-count buckets: a kernel instantiated for LMAX serves items with
 // N <= LMAX finite layers (its layer loops are unrolled to LMAX and skip the
 // levels beyond N).
-#define NR_BUCKETS(X) X(1) X(2) X(4) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40)
-constexpr int kBucketLmax[] = {1, 2, 4, 6, 8, 10, 12, 16, 20, 24, 32, 40};
+// (shallow and deep buckets are compiled in separate translation units)
+#define NR_BUCKETS_SHALLOW(X) X(1) X(2) X(4) X(6) X(8) X(10) X(12)
+#define NR_BUCKETS_DEEP(X) X(14) X(16) X(18) X(20) X(24) X(28) X(32) X(36) X(40)
+#define NR_BUCKETS(X) NR_BUCKETS_SHALLOW(X) NR_BUCKETS_DEEP(X)
+constexpr int kFirstDeepBucket = 7;
+constexpr int kBucketLmax[] = {1, 2, 4, 6, 8, 10, 12, 14, 16, 18, 20, 24, 28, 32, 36, 40};
 constexpr int kNumBuckets = sizeof(kBucketLmax) / sizeof(int);
 static_assert(kNumBuckets == NR_NUM_BUCKETS, "bucket table and ABI disagree");
 
@@ -106,6 +110,21 @@ hipError_t launch_grad(int precision, int bucket, bool store, bool tail, const K
 hipError_t launch_forward_f32(int op, const KernelArgs& a, int n_wu, hipStream_t st);
 hipError_t launch_grad_f32(int bucket, bool store, bool tail, const KernelArgs& a, int n_wu,
                            hipStream_t st);
+// Deep buckets (index >= kFirstDeepBucket): one object per (precision,
+// bucket), built from nr_kernels_bucket.hip, each exporting
+// launch_grad_deep_<F64|F32>_<layers>.
+#define NR_CAT4_(a, b, c, d) a##b##c##d
+#define NR_CAT4(a, b, c, d) NR_CAT4_(a, b, c, d)
+#define NR_DEEP_LAUNCHER(PREC, LM) NR_CAT4(launch_grad_deep_, PREC, _, LM)
+struct F64;
+struct F32;
+#define NR_DECLARE_DEEP(LM)                                                                  \
+  hipError_t NR_DEEP_LAUNCHER(F64, LM)(bool store, bool tail, const KernelArgs& a, int n_wu, \
+                                       hipStream_t st);                                      \
+  hipError_t NR_DEEP_LAUNCHER(F32, LM)(bool store, bool tail, const KernelArgs& a, int n_wu, \
+                                       hipStream_t st);
+NR_BUCKETS_DEEP(NR_DECLARE_DEEP)
+#undef NR_DECLARE_DEEP
 inline int store_max_layers(int precision) {
   return precision == NR_F32 ? kStoreMaxLayersF32 : kStoreMaxLayers;
 }

@@ -858,11 +858,8 @@ hipError_t launch_forward_p(int op, const KernelArgs& a, int n_wu, hipStream_t s
   return hipGetLastError();
 }
 
-template <class P>
-hipError_t launch_grad_p(int bucket, bool store, bool tail, const KernelArgs& a, int n_wu,
-                         hipStream_t st) {
-  if (n_wu <= 0) return hipSuccess;
-  switch (kBucketLmax[bucket]) {
+// Launch of one gradient bucket; BUCKETS is the list macro of the buckets
+// this translation unit compiles.
 #define NR_LAUNCH(LM, S)                                                                      \
   if (tail)                                                                                   \
     hipLaunchKernelGGL((k_loglik_grad<P, LM, S, true>), dim3(n_wu), dim3(64), 0, st, a);       \
@@ -881,12 +878,16 @@ hipError_t launch_grad_p(int bucket, bool store, bool tail, const KernelArgs& a,
       NR_LAUNCH(LM, false)                                                                    \
     }                                                                                         \
     return hipGetLastError();
-    NR_BUCKETS(NR_CASE)
-#undef NR_CASE
-#undef NR_LAUNCH
-    default:
-      return hipErrorInvalidValue;
+#define NR_DEFINE_GRAD_LAUNCHER(NAME, BUCKETS)                                                \
+  template <class P>                                                                          \
+  hipError_t NAME(int bucket, bool store, bool tail, const KernelArgs& a, int n_wu,          \
+                  hipStream_t st) {                                                           \
+    if (n_wu <= 0) return hipSuccess;                                                         \
+    switch (kBucketLmax[bucket]) {                                                            \
+      BUCKETS(NR_CASE)                                                                        \
+      default:                                                                                \
+        return hipErrorInvalidValue;                                                          \
+    }                                                                                         \
   }
-}
 
 }  // namespace nr

@@ -1,8 +1,10 @@
-// FP32 instantiation of the kernels (layer product and adjoint in float;
+// FP32 instantiation of the kernels, shallow buckets (layer product and adjoint in float;
 // kz0^2 - 4 pi drho, smearing, chi^2 and gradient accumulation in FP64).
 #include "nr_kernels.hpp"
 
 namespace nr {
+
+NR_DEFINE_GRAD_LAUNCHER(launch_grad_shallow, NR_BUCKETS_SHALLOW)
 
 hipError_t launch_forward_f32(int op, const KernelArgs& a, int n_wu, hipStream_t st) {
   return launch_forward_p<F32>(op, a, n_wu, st);
@@ -10,7 +12,7 @@ hipError_t launch_forward_f32(int op, const KernelArgs& a, int n_wu, hipStream_t
 
 hipError_t launch_grad_f32(int bucket, bool store, bool tail, const KernelArgs& a, int n_wu,
                            hipStream_t st) {
-  return launch_grad_p<F32>(bucket, store, tail, a, n_wu, st);
+  return launch_grad_shallow<F32>(bucket, store, tail, a, n_wu, st);
 }
 
 }  // namespace nr

@@ -1,8 +1,11 @@
-// FP64 instantiation of the kernels, the per-item constant prologue, the
-// per-item reductions, and the launch entry points of both precisions.
+// FP64 instantiation of the kernels (shallow buckets; the deep ones are in
+// nr_kernels_f64_deep.hip), the per-item constant prologue, the per-item
+// reductions, and the launch entry points of both precisions.
 #include "nr_kernels.hpp"
 
 namespace nr {
+
+NR_DEFINE_GRAD_LAUNCHER(launch_grad_shallow, NR_BUCKETS_SHALLOW)
 
 // One block of 64 per item, one lane per medium: the item's layer records
 // (doubles and their float copies for the FP32 variant).
@@ -119,8 +122,20 @@ hipError_t launch_forward(int precision, int op, const KernelArgs& a, int n_wu, 
 
 hipError_t launch_grad(int precision, int bucket, bool store, bool tail, const KernelArgs& a,
                        int n_wu, hipStream_t st) {
+  if (bucket >= kFirstDeepBucket) {
+    switch (kBucketLmax[bucket]) {
+#define NR_DEEP_CASE(LM)                                                             \
+  case LM:                                                                           \
+    return precision == NR_F32 ? NR_DEEP_LAUNCHER(F32, LM)(store, tail, a, n_wu, st) \
+                               : NR_DEEP_LAUNCHER(F64, LM)(store, tail, a, n_wu, st);
+      NR_BUCKETS_DEEP(NR_DEEP_CASE)
+#undef NR_DEEP_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
   return precision == NR_F32 ? launch_grad_f32(bucket, store, tail, a, n_wu, st)
-                             : launch_grad_p<F64>(bucket, store, tail, a, n_wu, st);
+                             : launch_grad_shallow<F64>(bucket, store, tail, a, n_wu, st);
 }
 
 hipError_t launch_reduce(int op, const ReduceArgs& a, hipStream_t st) {
