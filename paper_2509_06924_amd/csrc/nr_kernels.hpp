@@ -64,6 +64,10 @@ struct F64 {
   static constexpr int ef_levels(int lmax) {
     return lmax <= 10 ? (lmax + 1 < 8 ? lmax + 1 : 8) : (lmax + 1 < 17 ? lmax + 1 : 17);
   }
+  // recompute variant: keep the state of every second level only (the
+  // register tape of the deepest buckets otherwise spills to scratch)
+  static constexpr bool checkpoint(int lmax) { return lmax >= kCheckpointFrom; }
+  static constexpr int kCheckpointFrom = 28;
 };
 struct F32 {
   using real = float;
@@ -75,6 +79,8 @@ struct F32 {
   static constexpr int ef_levels(int lmax) {
     return lmax <= 16 ? (lmax + 1 < 16 ? lmax + 1 : 16) : (lmax + 1 < 35 ? lmax + 1 : 35);
   }
+  static constexpr bool checkpoint(int lmax) { return lmax >= kCheckpointFrom; }
+  static constexpr int kCheckpointFrom = 32;
 };
 
 // ---------------------------------------------------------------------------
@@ -611,23 +617,29 @@ struct EfCache {
 // recomputes each medium's wavevector and interface reciprocal, and, below
 // the KS cached levels, the phase and Nevot-Croce factor too.
 // ---------------------------------------------------------------------------
-template <class P, int LMAX, int KS>
+template <class P, int LMAX, int KS, bool CK>
 __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const Layers<P>& L,
                                                       EfCache<typename P::real, KS>& ef,
                                                       Accum<LMAX>& acc, int lane, double q,
                                                       double wk, bool& edge) {
   using Re = typename P::real;
   using Cx = cx<Re>;
+  static_assert(!CK || LMAX % 2 == 0, "checkpointed tape needs an even depth");
   const double kz0sq = kz0_squared(q);
   const Cx kz0 = fronting_kz<P>(q);
-  Cx tapeP[LMAX + 1], tapeQ[LMAX + 1];
+  // state tape: every level, or (CK) every second one; level j (odd) is then
+  // re-formed in the adjoint by applying level j + 1 to the state at j + 1
+  constexpr int NT = CK ? LMAX / 2 + 1 : LMAX + 1;
+  Cx tapeP[NT], tapeQ[NT];
   Cx kzn = medium_root(L, kz0sq, LMAX + 1, edge).kz;
   Cx Pv = mk(Re(1), Re(0)), Qv = mk(Re(0), Re(0));
 #pragma unroll
   for (int jj = LMAX; jj >= 0; --jj) {
     const Cx kzc = (jj == 0) ? kz0 : medium_root(L, kz0sq, jj, edge).kz;
-    tapeP[jj] = Pv;
-    tapeQ[jj] = Qv;
+    if (!CK || jj % 2 == 0) {
+      tapeP[CK ? jj / 2 : jj] = Pv;
+      tapeQ[CK ? jj / 2 : jj] = Qv;
+    }
     const Iface<Re> it = interface_coeffs(T, kzc, kzn, L.Nr(jj), L.Ni(jj), L.C(jj));
     const Cx Pn = Pv + it.rp * Qv;
     const Cx t = it.rp * Pv + Qv;
@@ -648,42 +660,84 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
   const Cx rbar = static_cast<Re>(2.0 * wk) * r;
   Cx Pb = cmulc(-(r * iP), rbar);
   Cx Qb = cmulc(iP, rbar);
-  Cx kzc = kz0;
-  Re iac = Re(0);
   Cx kzbc = mk(Re(0), Re(0));
-#pragma unroll
-  for (int jj = 0; jj <= LMAX; ++jj) {
-    const RootT<Re> rn = medium_root(L, kz0sq, jj + 1);
-    const Re C = L.C(jj);
-    const bool ph = jj >= 1;
-    const Re D = ph ? L.D(jj) : Re(0);
+
+  // the coefficients of level jj (kz_jj = kzc known), recomputed or from the
+  // LDS cache
+  struct Lev {
+    RootT<Re> rn;  // medium jj + 1
     Iface<Re> it;
     Cx e;
+    Re C, D;
+  };
+  auto level = [&](int jj, Cx kzc) {
+    Lev o;
+    o.rn = medium_root(L, kz0sq, jj + 1);
+    o.C = L.C(jj);
+    const bool ph = jj >= 1;
+    o.D = ph ? L.D(jj) : Re(0);
     if (jj < KS) {
-      const Cx s = crecip(kzc + rn.kz);
-      it.s2 = s * s;
-      it.f = mk(ef.v[jj][2][lane], ef.v[jj][3][lane]);
-      it.rp = (mk(L.Nr(jj), L.Ni(jj)) * it.s2) * it.f;
-      it.kk = kzc * rn.kz;
-      e = ph ? mk(ef.v[jj][0][lane], ef.v[jj][1][lane]) : mk(Re(1), Re(0));
+      const Cx s = crecip(kzc + o.rn.kz);
+      o.it.s2 = s * s;
+      o.it.f = mk(ef.v[jj][2][lane], ef.v[jj][3][lane]);
+      o.it.rp = (mk(L.Nr(jj), L.Ni(jj)) * o.it.s2) * o.it.f;
+      o.it.kk = kzc * o.rn.kz;
+      o.e = ph ? mk(ef.v[jj][0][lane], ef.v[jj][1][lane]) : mk(Re(1), Re(0));
     } else {
-      it = interface_coeffs(T, kzc, rn.kz, L.Nr(jj), L.Ni(jj), C);
-      e = ph ? layer_phase(T, kzc, D) : mk(Re(1), Re(0));
+      o.it = interface_coeffs(T, kzc, o.rn.kz, L.Nr(jj), L.Ni(jj), o.C);
+      o.e = ph ? layer_phase(T, kzc, o.D) : mk(Re(1), Re(0));
     }
-    const AdjStep<Re> st = adjoint_step(tapeP[jj], tapeQ[jj], Pb, Qb, kzc, rn.kz, it, C, ph, e, D);
+    return o;
+  };
+  // the adjoint of level jj from the state (Ps, Qs) entering it
+  auto step = [&](int jj, const Lev& lv, Cx Ps, Cx Qs, Cx kzc, Re iac) {
+    const bool ph = jj >= 1;
+    const AdjStep<Re> st =
+        adjoint_step(Ps, Qs, Pb, Qb, kzc, lv.rn.kz, lv.it, lv.C, ph, lv.e, lv.D);
     kzbc += st.kzb_c;
-    acc_re_dot(acc.Hs[jj + 1], st.ub, it.kk);
+    acc_re_dot(acc.Hs[jj + 1], st.ub, lv.it.kk);
     if (ph) {
       acc_dd(acc.Hd[jj], kzc, st.w);
       acc_wbar(acc.Hw[jj], kzc, iac, kzbc);
     }
-    if (jj == LMAX) acc_wbar(acc.Hw[jj + 1], rn.kz, rn.inv_abs2, st.kzb_n);
+    if (jj == LMAX) acc_wbar(acc.Hw[jj + 1], lv.rn.kz, lv.rn.inv_abs2, st.kzb_n);
     Pb = st.Pb;
     Qb = st.Qb;
-    kzc = rn.kz;
-    iac = rn.inv_abs2;
     kzbc = st.kzb_n;
-    __builtin_amdgcn_sched_barrier(0x0100);  // only LDS reads may move across
+  };
+
+  Cx kzc = kz0;
+  Re iac = Re(0);
+  if constexpr (!CK) {
+#pragma unroll
+    for (int jj = 0; jj <= LMAX; ++jj) {
+      const Lev lv = level(jj, kzc);
+      step(jj, lv, tapeP[jj], tapeQ[jj], kzc, iac);
+      kzc = lv.rn.kz;
+      iac = lv.rn.inv_abs2;
+      __builtin_amdgcn_sched_barrier(0x0100);  // only LDS reads may move across
+    }
+  } else {
+    {
+      const Lev l0 = level(0, kzc);
+      step(0, l0, tapeP[0], tapeQ[0], kzc, iac);
+      kzc = l0.rn.kz;
+      iac = l0.rn.inv_abs2;
+    }
+    __builtin_amdgcn_sched_barrier(0x0100);
+#pragma unroll
+    for (int jj = 1; jj <= LMAX; jj += 2) {
+      const Lev la = level(jj, kzc);
+      const Lev lb = level(jj + 1, la.rn.kz);
+      const Cx P1 = tapeP[(jj + 1) / 2], Q1 = tapeQ[(jj + 1) / 2];
+      const Cx P0 = P1 + lb.it.rp * Q1;
+      const Cx Q0 = lb.e * (lb.it.rp * P1 + Q1);
+      step(jj, la, P0, Q0, kzc, iac);
+      step(jj + 1, lb, P1, Q1, la.rn.kz, la.rn.inv_abs2);
+      kzc = lb.rn.kz;
+      iac = lb.rn.inv_abs2;
+      __builtin_amdgcn_sched_barrier(0x0100);  // only LDS reads may move across
+    }
   }
   return (double)cabs2(r);
 }
@@ -733,7 +787,8 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX)) void k_loglik_grad(KernelAr
     if constexpr (STORE)
       R = node_grad_store<P, LMAX>(s.tab, L, tape, acc, lane, q, wk, edge);
     else
-      R = node_grad_recompute<P, LMAX, KS>(s.tab, L, efc, acc, lane, q, wk, edge);
+      R = node_grad_recompute<P, LMAX, KS, P::checkpoint(LMAX)>(s.tab, L, efc, acc, lane, q, wk,
+                                                                edge);
     Rsm += wk * R;
   }
   // the item was evaluated at depth LMAX: the copies of the backing below it
