@@ -55,32 +55,30 @@ struct F64 {
   using real = double;
   static constexpr int kStoreMax = kStoreMaxLayers;
   static constexpr int kSlimMax = 6;
-  static constexpr int min_waves(int) { return 1; }
+  static constexpr int min_waves(int lmax, bool store) { return (!store && lmax <= 14) ? 2 : 1; }
   // recompute variant: levels whose phase and Nevot-Croce factor are kept in
   // LDS (2 KB per level per wave; ~36 KB of the 40 KB a wave may use at one
   // wave per SIMD)
   // (up to 10 layers the kernel fits two waves per SIMD in registers, so its
   // LDS is held to 20 KB: 8 levels)
   static constexpr int ef_levels(int lmax) {
-    return lmax <= 10 ? (lmax + 1 < 8 ? lmax + 1 : 8) : (lmax + 1 < 17 ? lmax + 1 : 17);
+    return lmax <= 14 ? (lmax + 1 < 8 ? lmax + 1 : 8) : (lmax + 1 < 17 ? lmax + 1 : 17);
   }
   // recompute variant: keep the state of every second level only (the
   // register tape of the deepest buckets otherwise spills to scratch)
-  static constexpr bool checkpoint(int lmax) { return lmax >= kCheckpointFrom; }
-  static constexpr int kCheckpointFrom = 28;
+  static constexpr bool checkpoint(int lmax) { return lmax == 12 || lmax == 14 || lmax >= 28; }
 };
 struct F32 {
   using real = float;
   static constexpr int kStoreMax = kStoreMaxLayersF32;
   static constexpr int kSlimMax = 0;
-  static constexpr int min_waves(int lmax) { return lmax <= 10 ? 2 : 1; }
+  static constexpr int min_waves(int lmax, bool) { return lmax <= 10 ? 2 : 1; }
   // 1 KB per level; up to 16 layers the kernel keeps two waves per SIMD, so
   // its LDS stays within 20 KB
   static constexpr int ef_levels(int lmax) {
     return lmax <= 16 ? (lmax + 1 < 16 ? lmax + 1 : 16) : (lmax + 1 < 35 ? lmax + 1 : 35);
   }
-  static constexpr bool checkpoint(int lmax) { return lmax >= kCheckpointFrom; }
-  static constexpr int kCheckpointFrom = 32;
+  static constexpr bool checkpoint(int lmax) { return lmax >= 32; }
 };
 
 // ---------------------------------------------------------------------------
@@ -752,7 +750,7 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
 //   [3 + 3NR + m]  sum Re(conj(ubar) kz_{m-1} kz_m)   (sigma_m factor applied later)
 // ---------------------------------------------------------------------------
 template <class P, int LMAX, bool STORE, bool TAIL>
-__global__ __launch_bounds__(64, P::min_waves(LMAX)) void k_loglik_grad(KernelArgs a) {
+__global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(KernelArgs a) {
   using Re = typename P::real;
   __shared__ Shared s;
   using Tape = typename std::conditional<STORE, GradTape<Re, LMAX>, char>::type;
