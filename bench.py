@@ -120,20 +120,32 @@ def make_workload(name):
     return b, cfg
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(batch, target_s=15.0):
     """The oracle (CPU, FP64, complex-step gradient) on a bounded sample of the
-    same workload, all host threads; returns layer-steps/s of logL + gradient."""
+    same workload, all host threads (up to 16); returns layer-steps/s of
+    logL + gradient, plus the forward-only logL rate on the same sample and
+    the one-thread gradient rate on a smaller one."""
     import numpy as np
 
     import oracle
     nthreads = max(1, min(oracle.max_threads(), os.cpu_count() or 1, 16))
 
-    def run(items):
+    def run(items, grad=True, threads=nthreads):
         sub = batch.subset(items)
         t0 = time.perf_counter()
         oracle.loglik_grad_batch(sub.q_off, sub.Q, sub.Robs, sub.Rerr, sub.dq_over_q,
                                  sub.dataset_of_item, sub.row_off, sub.layers, sub.scale,
-                                 sub.bkg, want_grad=True, nthreads=nthreads)
+                                 sub.bkg, want_grad=grad, nthreads=threads)
         return time.perf_counter() - t0, sub.layer_steps()
 
     t1, _ = run(np.arange(min(nthreads, batch.n_items)))
@@ -141,9 +153,18 @@ def cpu_baseline(batch, target_s=15.0):
     rounds = max(1, int(target_s / per_round))
     n = min(batch.n_items, rounds * nthreads)
     t, ls = run(np.arange(n))
+    tf, lsf = run(np.arange(n), grad=False)
+    n1 = max(1, min(batch.n_items, int(0.2 * target_s / per_round)))
+    t_1, ls_1 = run(np.arange(n1), threads=1)
     return {"value": ls / t, "unit": UNIT, "cores": nthreads, "kind": "oracle",
             "sample": f"first {n} items of the workload ({ls:.3e} layer-steps, {t:.1f} s, "
-                      f"complex-step gradient, OpenMP over items)"}
+                      f"complex-step gradient, OpenMP over items)",
+            "forward_only_value": lsf / tf,
+            "one_thread_value": ls_1 / t_1,
+            "one_thread_sample": f"first {n1} items, {t_1:.1f} s",
+            "host": {"cpu": _cpu_model(), "nproc": os.cpu_count()},
+            "note": "the complex-step gradient costs about 4x a forward evaluation per "
+                    "parameter: a correctness referee, not a tuned CPU gradient"}
 
 
 def main():
