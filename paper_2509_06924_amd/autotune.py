@@ -27,6 +27,8 @@ from . import Plan, Problem, bucket_lmax
 
 XCD_RUNS = (1, 4, 8, 16, 32)
 MIN_GAIN = 0.03
+WARMUP_S = 0.3
+CONFIRM_ROUNDS = 3
 
 
 def default_cache_path():
@@ -110,8 +112,11 @@ def tune(batch, precision=_n.NR_F64, device="cuda", cache=None, reps=7, verbose=
 
     base = Problem.from_batch(batch, device=dev, precision=precision)
     out = base.loglik_grad()
-    # warm the device up (clocks, caches) before the first timed schedule
-    for _ in range(3):
+    # warm the device up (clocks, caches) for a fixed time before the first
+    # timed schedule
+    import time as _time
+    t_end = _time.perf_counter() + WARMUP_S
+    while _time.perf_counter() < t_end:
         _time_call(base, out, 1)
 
     def problem(opts):
@@ -152,6 +157,17 @@ def tune(batch, precision=_n.NR_F64, device="cuda", cache=None, reps=7, verbose=
             consider({**best, "xcd_run": run})
     consider({**best, "pack_tails": 1 - best["pack_tails"]})
 
+    # confirm against the default, interleaved so that drift cancels
+    if best != trials[0][0]:
+        p_def, p_best = problem(trials[0][0]), problem(best)
+        td, tb = [], []
+        for _ in range(CONFIRM_ROUNDS):
+            td.append(_time_call(p_def, out, reps))
+            tb.append(_time_call(p_best, out, reps))
+        if np.median(tb) >= np.median(td) * (1.0 - MIN_GAIN):
+            best, best_t = trials[0][0], float(np.median(td))
+        else:
+            best_t = float(np.median(tb))
     record = {"options": best, "ms": best_t, "default_ms": trials[0][1],
               "trials": len(trials)}
     if use_cache:
