@@ -211,5 +211,53 @@ def loglik_grad_batch(q_off, Q, Robs, Rerr, dq_over_q, dataset_of_item, row_off,
     return ll, g, gi.reshape(n_items, 2)
 
 
+def reflectivity_dq_cs(rows, q):
+    """dR/dq of the unsmeared R (complex step through q)."""
+    r, L = _rows(rows)
+    q = _vec(q)
+    out = np.empty_like(q)
+    _check(lib().orc_reflectivity_dq_cs(_I(L), _p(r), _I(q.size), _p(q), _p(out)))
+    return out
+
+
+def model_curve_res(rows, scale, bkg, Q, dq_over_q, dQ=None):
+    """R_hat with per-point FWHMs dQ (None: dq_over_q * Q)."""
+    r, L = _rows(rows)
+    Q = _vec(Q)
+    out = np.empty_like(Q)
+    dq = None if dQ is None else _vec(dQ)
+    _check(lib().orc_model_curve_res(_I(L), _p(r), _D(scale), _D(bkg), _I(Q.size), _p(Q),
+                                     _D(dq_over_q), None if dq is None else _p(dq), _p(out)))
+    return out
+
+
+def loglik_grad_res_cs(rows, scale, bkg, Q, Robs, Rerr, dq_over_q, dQ=None):
+    """(logL, g_rows, g_inst, dlogL/d(dQ/Q)) by complex step; per-point FWHMs
+    dQ are data (their derivative is not taken; g_res is then 0)."""
+    r, L = _rows(rows)
+    Q, Robs, Rerr = _vec(Q), _vec(Robs), _vec(Rerr)
+    dq = None if dQ is None else _vec(dQ)
+    ll = ctypes.c_double()
+    gr = ctypes.c_double()
+    g = np.zeros_like(r)
+    gi = np.zeros(2)
+    _check(lib().orc_loglik_grad_res_cs(
+        _I(L), _p(r), _D(scale), _D(bkg), _I(Q.size), _p(Q), _p(Robs), _p(Rerr),
+        _D(dq_over_q), None if dq is None else _p(dq), ctypes.byref(ll), _p(g), _p(gi),
+        ctypes.byref(gr)))
+    return ll.value, g, gi, gr.value
+
+
+def loglik_res_fd(rows, scale, bkg, Q, Robs, Rerr, dq_over_q, rel_step=1e-3):
+    """Richardson difference of logL in dQ/Q."""
+    r, L = _rows(rows)
+    Q, Robs, Rerr = _vec(Q), _vec(Robs), _vec(Rerr)
+    gr = ctypes.c_double()
+    _check(lib().orc_loglik_res_fd(_I(L), _p(r), _D(scale), _D(bkg), _I(Q.size), _p(Q),
+                                   _p(Robs), _p(Rerr), _D(dq_over_q), _D(rel_step),
+                                   ctypes.byref(gr)))
+    return gr.value
+
+
 def max_threads():
     return lib().orc_max_threads()

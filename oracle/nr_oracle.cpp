@@ -247,18 +247,20 @@ static inline double node_q(double Q, double dq_over_q, double t) {
 // Abeles reflection amplitude at one momentum transfer q.  Z is cplx for the
 // value, BC for complex-step derivatives; rows are lifted to Z.
 // ---------------------------------------------------------------------------
+// The product depends on q only through kz0^2 = q^2/4 (in every w_j) and the
+// fronting wavevector kz0 = q/2; abeles_amplitude_k takes both (as Z, so that
+// q itself can carry a complex-step perturbation).
 template <class Z>
-static Z abeles_amplitude(int L, const Z* rows, double q) {
+static Z abeles_amplitude_k(int L, const Z* rows, Z kz0sq, Z kz0) {
   const int N = L;
   std::vector<Z> kz(N + 2);
-  const double kz0sq = 0.25 * q * q;
-  kz[0] = Z(cplx(0.5 * q, 0.0));
+  kz[0] = kz0;
   const Z rho0 = rows[0 * 4 + 1];
   for (int j = 1; j <= N + 1; ++j) {
     const Z rho_re = rows[j * 4 + 1];
     const Z rho_im = abs_real(rows[j * 4 + 2]);
     // w = 0.25 q q - 4 pi (rho_re_j - rho_re_0) - i 4 pi |rho_im_j|
-    Z re_part = Z(kz0sq) - FOURPI * (rho_re - rho0);
+    Z re_part = kz0sq - FOURPI * (rho_re - rho0);
     Z im_part = -(FOURPI * rho_im);  // -0.0 when rho_im = 0
     kz[j] = kz_root(make_xy(re_part, im_part));
   }
@@ -293,8 +295,21 @@ static Z abeles_amplitude(int L, const Z* rows, double q) {
 }
 
 template <class Z>
+static Z abeles_amplitude(int L, const Z* rows, double q) {
+  const double kz0sq = 0.25 * q * q;
+  return abeles_amplitude_k(L, rows, Z(kz0sq), Z(cplx(0.5 * q, 0.0)));
+}
+
+template <class Z>
 static Z reflectivity(int L, const Z* rows, double q) {
   Z r = abeles_amplitude(L, rows, q);
+  return r * conj_i(r);
+}
+
+// R at a lifted momentum transfer (its J-part differentiates through q).
+static BC reflectivity_bcq(int L, const BC* rows, BC q) {
+  const BC kz0sq = (0.25 * q) * q;
+  BC r = abeles_amplitude_k(L, rows, kz0sq, 0.5 * q);
   return r * conj_i(r);
 }
 
@@ -311,6 +326,49 @@ static void model_curve(int L, const Z* rows, Z scale, Z bkg, int nq,
     }
     Rhat[i] = scale * Rsm + bkg;
   }
+}
+
+// Resolution given per point (Sec. 3 pointwise Gaussian smearing, Sec. 4.1
+// FWHM estimates per point) or as a free relative width (Sec. 4.2: the
+// smearing size is an unknown).  For a smeared dataset (dq_over_q > 0) the
+// nodes of point i are Q_i + s_i t_k with s_i = dQ_i / (2 sqrt(2 ln 2)) when
+// per-point FWHMs dQ are given, else s_i = (dq_over_q Q_i) / (2 sqrt(2 ln 2));
+// the weights w_k are the same normalised Gaussian weights either way.
+// dqq_j: dq_over_q carrying a J-perturbation (complex step on the width).
+static void model_curve_res(int L, const BC* rows, BC scale, BC bkg, int nq, const double* Q,
+                            double dq_over_q, const double* dQ, BC dqq_j, BC* Rhat) {
+  SmearRule rule = make_rule(dq_over_q);
+  for (int i = 0; i < nq; ++i) {
+    BC Rsm(0.0);
+    for (int k = 0; k < rule.K; ++k) {
+      BC q;
+      if (rule.K == 1) {
+        q = BC(Q[i]);
+      } else if (dQ) {
+        const double s = dQ[i] / FWHM_PER_SIGMA;
+        q = BC(Q[i] + s * rule.t[k]);
+      } else {
+        BC s = dqq_j * Q[i];
+        s = s / FWHM_PER_SIGMA;
+        q = BC(Q[i]) + s * rule.t[k];
+      }
+      Rsm = Rsm + rule.w[k] * reflectivity_bcq(L, rows, q);
+    }
+    Rhat[i] = scale * Rsm + bkg;
+  }
+}
+
+static BC loglik_res(int L, const BC* rows, BC scale, BC bkg, int nq, const double* Q,
+                     const double* Robs, const double* Rerr, double dq_over_q, const double* dQ,
+                     BC dqq_j) {
+  std::vector<BC> Rhat(nq);
+  model_curve_res(L, rows, scale, bkg, nq, Q, dq_over_q, dQ, dqq_j, Rhat.data());
+  BC s(0.0);
+  for (int i = 0; i < nq; ++i) {
+    BC z = (Rhat[i] - BC(Robs[i])) / Rerr[i];
+    s = s + (-0.5) * (z * z) - BC(std::log(Rerr[i]) + HALF_LN_2PI);
+  }
+  return s;
 }
 
 template <class Z>
@@ -702,6 +760,72 @@ int orc_loglik_grad_batch(int n_datasets, const int64_t* q_off, const double* Q,
                            dq_over_q[ds]);
   }
   return bad ? -1 : 0;
+}
+
+// --- resolution: pointwise widths and the derivative w.r.t. dQ/Q ---------
+
+// dR/dq (complex step through q) of the unsmeared R at nq momentum transfers.
+int orc_reflectivity_dq_cs(int L, const double* rows, int nq, const double* q, double* dRdq) {
+  if (L < 0 || nq < 0) return -1;
+  std::vector<BC> zr(rows, rows + (L + 2) * 4);
+  for (int i = 0; i < nq; ++i) {
+    const double h = 1e-20 * std::fmax(1.0, std::fabs(q[i]));
+    BC v = reflectivity_bcq(L, zr.data(), BC(cplx(q[i]), cplx(h)));
+    dRdq[i] = v.b.real() / h;
+  }
+  return 0;
+}
+
+// R_hat with per-point FWHMs dQ (NULL: dq_over_q * Q) on a smeared dataset.
+int orc_model_curve_res(int L, const double* rows, double scale, double bkg, int nq,
+                        const double* Q, double dq_over_q, const double* dQ, double* Rhat) {
+  if (L < 0 || nq < 0 || !(dq_over_q >= 0.0)) return -1;
+  std::vector<BC> zr(rows, rows + (L + 2) * 4), out(nq);
+  model_curve_res(L, zr.data(), BC(scale), BC(bkg), nq, Q, dq_over_q, dQ, BC(dq_over_q),
+                  out.data());
+  for (int i = 0; i < nq; ++i) Rhat[i] = out[i].a.real();
+  return 0;
+}
+
+// logL and its complex-step gradient with the resolution as data (dQ) or as a
+// parameter: g_res = dlogL/d(dQ/Q) (0 when dQ is given or the dataset is
+// unsmeared).
+int orc_loglik_grad_res_cs(int L, const double* rows, double scale, double bkg, int nq,
+                           const double* Q, const double* Robs, const double* Rerr,
+                           double dq_over_q, const double* dQ, double* logL, double* g_rows,
+                           double* g_inst, double* g_res) {
+  if (L < 0 || nq < 0 || !(dq_over_q >= 0.0)) return -1;
+  std::vector<BC> zr0(rows, rows + (L + 2) * 4);
+  *logL = loglik_res(L, zr0.data(), BC(scale), BC(bkg), nq, Q, Robs, Rerr, dq_over_q, dQ,
+                     BC(dq_over_q)).a.real();
+  auto eval = [&](const BC* zr, BC sc, BC bk) {
+    return loglik_res(L, zr, sc, bk, nq, Q, Robs, Rerr, dq_over_q, dQ, BC(dq_over_q));
+  };
+  complex_step_grad(L, rows, scale, bkg, eval, g_rows, g_inst);
+  *g_res = 0.0;
+  if (dq_over_q > 0.0 && !dQ) {
+    const double h = 1e-20 * std::fmax(1e-2, dq_over_q);
+    BC v = loglik_res(L, zr0.data(), BC(scale), BC(bkg), nq, Q, Robs, Rerr, dq_over_q, nullptr,
+                      BC(cplx(dq_over_q), cplx(h)));
+    *g_res = v.b.real() / h;
+  }
+  return 0;
+}
+
+// Richardson difference of logL in dQ/Q (step rel_step * dQ/Q).
+int orc_loglik_res_fd(int L, const double* rows, double scale, double bkg, int nq,
+                      const double* Q, const double* Robs, const double* Rerr,
+                      double dq_over_q, double rel_step, double* g_res) {
+  if (L < 0 || nq < 0 || !(dq_over_q > 0.0)) return -1;
+  std::vector<BC> zr(rows, rows + (L + 2) * 4);
+  auto f = [&](double d) {
+    return loglik_res(L, zr.data(), BC(scale), BC(bkg), nq, Q, Robs, Rerr, d, nullptr, BC(d))
+        .a.real();
+  };
+  const double h = rel_step * dq_over_q;
+  *g_res = (8.0 * (f(dq_over_q + h) - f(dq_over_q - h)) -
+            (f(dq_over_q + 2.0 * h) - f(dq_over_q - 2.0 * h))) / (12.0 * h);
+  return 0;
 }
 
 int orc_max_threads(void) {
