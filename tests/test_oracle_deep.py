@@ -1,0 +1,94 @@
+"""Pins of the oracle on deep stacks (microsliced SLD profiles, hundreds to
+thousands of slabs): the Abeles product against the independent Parratt
+recursion; a thick layer cut into thin slices of the same SLD reflects
+exactly like the layer; and the complex-step gradient against Richardson
+differences and against the sliced-layer identities (every slice's thickness
+derivative equals the layer's; the slices' SLD derivatives sum to the
+layer's)."""
+import numpy as np
+import pytest
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.max(np.abs(a - b) / np.abs(b)))
+
+
+def smooth_profile(rng, L, dz=3.0):
+    """A microsliced profile: L slices of dz A sampling a smooth SLD curve
+    (two interdiffused films on silicon), small absorption (away from the
+    kink of |rho_im| at 0, so that differences across it stay one-sided),
+    roughness 0.5 A."""
+    z = (np.arange(L) + 0.5) * dz
+    span = L * dz
+    c1, c2 = rng.uniform(0.2, 0.4) * span, rng.uniform(0.6, 0.8) * span
+    w = rng.uniform(0.03, 0.08) * span
+    rho = (1.0e-6 + 3.0e-6 / (1 + np.exp(-(z - c1) / w)) - 2.0e-6 / (1 + np.exp(-(z - c2) / w)))
+    rows = np.zeros((L + 2, 4))
+    rows[0] = [0, 0.0, 0, 0]
+    rows[1:L + 1, 0] = dz
+    rows[1:L + 1, 1] = rho
+    rows[1:L + 1, 2] = 5e-8
+    rows[1:L + 1, 3] = 0.5
+    rows[L + 1] = [0, 2.07e-6, 5e-8, 3.0]
+    return rows
+
+
+@pytest.mark.parametrize("L", [100, 500, 2047])
+def test_deep_abeles_equals_parratt(orc, L):
+    rng = np.random.default_rng(700 + L)
+    q = np.geomspace(0.004, 0.3, 60)
+    rows = smooth_profile(rng, L)
+    # rounding grows with depth; the two recursions accumulate it differently
+    assert rel(orc.reflectivity(rows, q), orc.reflectivity_parratt(rows, q)) < 1e-11
+
+
+def _sliced(n, d=600.0, rho=3.5e-6, top_sigma=4.0):
+    rows = np.zeros((n + 2, 4))
+    rows[0] = [0, 0.0, 0, 0]
+    rows[1:n + 1] = [d / n, rho, 0.0, 0.0]
+    rows[1, 3] = top_sigma
+    rows[n + 1] = [0, 2.07e-6, 0, 3.0]
+    return rows
+
+
+def test_slices_reflect_like_the_layer(orc):
+    q = np.geomspace(0.005, 0.3, 80)
+    one = _sliced(1)
+    for n in (2, 75, 300):
+        assert rel(orc.reflectivity(_sliced(n), q), orc.reflectivity(one, q)) < 1e-11
+
+
+def test_deep_gradient_complex_step_vs_richardson(orc):
+    rng = np.random.default_rng(711)
+    rows = smooth_profile(rng, 120)
+    Q = np.geomspace(0.01, 0.2, 12)
+    R = orc.model_curve(rows, 1.0, 1e-7, Q, 0.0)
+    Robs = R * (1 + 0.05 * rng.standard_normal(Q.size))
+    Rerr = 0.03 * Robs
+    _, g, gi = orc.loglik_grad_cs(rows, 1.0, 1e-7, Q, Robs, Rerr, 0.0)
+    gf, gif = orc.loglik_grad_fd(rows, 1.0, 1e-7, Q, Robs, Rerr, 0.0)
+    units = np.array([1.0, 1e-6, 1e-6, 1.0])
+    a = np.concatenate([(g * units).ravel(), gi * [1.0, 1e-7]])
+    b = np.concatenate([(gf * units).ravel(), gif * [1.0, 1e-7]])
+    assert np.max(np.abs(a - b)) <= 1e-6 * np.max(np.abs(a))
+
+
+def test_sliced_layer_gradient_identities(orc):
+    n = 40
+    Q = np.geomspace(0.01, 0.25, 15)
+    one, cut = _sliced(1), _sliced(n)
+    R = orc.model_curve(one, 1.0, 1e-7, Q, 0.03)
+    rng = np.random.default_rng(712)
+    Robs = R * (1 + 0.05 * rng.standard_normal(Q.size))
+    Rerr = 0.03 * Robs
+    l1, g1, _ = orc.loglik_grad_cs(one, 1.0, 1e-7, Q, Robs, Rerr, 0.03)
+    ln, gn, _ = orc.loglik_grad_cs(cut, 1.0, 1e-7, Q, Robs, Rerr, 0.03)
+    assert abs(ln - l1) <= 1e-10 * abs(l1)
+    # R depends on the slices' thicknesses through their sum only
+    assert np.allclose(gn[1:n + 1, 0], g1[1, 0], rtol=1e-8, atol=0)
+    # moving every slice's SLD together moves the layer's
+    assert abs(np.sum(gn[1:n + 1, 1]) - g1[1, 1]) <= 1e-8 * abs(g1[1, 1])
+    # the backing and the top interface are shared
+    assert abs(gn[n + 1, 1] - g1[2, 1]) <= 1e-8 * abs(g1[2, 1])
+    assert abs(gn[1, 3] - g1[1, 3]) <= 1e-8 * abs(g1[1, 3])
