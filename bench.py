@@ -479,6 +479,102 @@ def ragged_hmc_row(nr, precision, n_steps=10):
             "layer_steps_per_step": batch.layer_steps()}
 
 
+def hmc_driver_row(nr, n_leapfrog=4):
+    """16384 ragged chains (the leapfrog workload above): whole HMC transitions
+    of the driver (momentum draws, n leapfrog steps in pre-scaled coordinates,
+    Metropolis-Hastings accept) captured in one HIP graph."""
+    import numpy as np
+
+    from paper_2509_06924_amd import inputs
+    batch = inputs.c4_ragged()
+    prob = nr.Problem.from_batch(batch, device="cuda:0")
+    R = batch.layers.shape[0]
+    # pre-scaled coordinates: z in natural units (d, sigma 1 A; rho 1e-6; bkg 1e-7)
+    b_rows = np.tile(np.array(NATURAL_UNITS), (R, 1))
+    b_inst = np.tile(np.array([1.0, 1e-7]), (batch.n_items, 1))
+    h = nr.HMC(prob, b_rows=b_rows, b_inst=b_inst, step=2e-5, n_leapfrog=n_leapfrog,
+               seed=2509).init(from_theta=True)
+    graph = h.graph(n_transitions=1)
+    dt = _timed(graph.launch, 3)
+    graph.close()
+    n_acc = int(h.n_accept.sum().item())
+    n_tr = int(h.n_accept.numel()) * 4  # the warm-up launch plus three timed ones
+    out = {"what": f"16384 ragged chains, L 2..40, nQ 100..1000, dQ/Q 2-8%: HIP-graph HMC "
+                   f"transition ({n_leapfrog} leapfrog steps, Philox momenta, MH accept)",
+           "ms_per_transition": dt * 1e3,
+           "value": n_leapfrog * batch.layer_steps() / dt, "unit": UNIT,
+           "accept_rate": n_acc / n_tr,
+           "divergent": int(h.n_divergent.sum().item())}
+    h.close()
+    return out
+
+
+def deep_stack_row(nr, reps=3):
+    """64 microsliced profiles x 1000 slabs x 200 Q, 5% dQ/Q: logL + gradient
+    through the parallel-in-layers scan (one wave per data point), and the
+    forward-only value kernel on the same batch."""
+    import torch
+
+    from paper_2509_06924_amd import inputs
+    batch = inputs.microsliced()
+    prob = nr.Problem.from_batch(batch, device="cuda:0")
+    out = prob.loglik_grad()
+    stream = torch.cuda.current_stream()
+    dt = _timed(lambda: prob.loglik_grad(out=out, stream=stream), reps)
+    dtf = _timed(lambda: prob.loglik(stream=stream), reps)
+    ls = batch.layer_steps()
+    return {"what": "64 microsliced profiles x 1000 slabs x 200 Q, 5% dQ/Q: parallel-in-layers "
+                    "scan gradient (FP64), one wave per data point",
+            "ms_per_step": dt * 1e3, "value": ls / dt, "unit": UNIT,
+            "frac_fp64_peak": FLOP_PER_LAYER_STEP * ls / dt / FP64_VALU_PEAK,
+            "forward_only_ms": dtf * 1e3, "layer_steps_per_step": ls}
+
+
+def vi_mvn_row(nr, reps=5):
+    """The full-rank Gaussian VI of the paper's co-fit study: 100 restarts x
+    8 draws of a 12-layer stack over 300 Q, 5% dQ/Q, one Adam step each."""
+    import numpy as np
+
+    from paper_2509_06924_amd import inputs
+    R, S, L = 100, 8, 12
+    rng = np.random.default_rng(13)
+    template = inputs.draw_stack(rng, L, d=(20.0, 80.0), rho=(0.5e-6, 4.5e-6),
+                                 sigma=(2.0, 10.0))
+    Q = inputs.log_grid(0.005, 0.3, 300)
+    Robs, err = inputs.synthetic_curve(Q, rng)
+    batch = inputs._pack("mvn", [(Q, Robs, err, 0.05)], [(0, template, 1.0, 1e-7)] * (R * S),
+                         {})
+    prob = nr.Problem.from_batch(batch, device="cuda:0")
+    nrow = L + 2
+    P = 4 * nrow + 2
+    kind = np.zeros(P, np.uint8)
+    a = np.zeros(P)
+    b = np.ones(P)
+    for r in range(1, nrow):
+        kind[4 * r + 1], b[4 * r + 1] = nr.NR_TF_AFFINE, 1e-6
+        kind[4 * r + 3], b[4 * r + 3] = nr.NR_TF_LOGIT, 30.0
+        if r < nrow - 1:
+            kind[4 * r] = nr.NR_TF_LOG
+    kind[P - 2], a[P - 2], b[P - 2] = nr.NR_TF_AFFINE, 1.0, 0.01
+    kind[P - 1], b[P - 1] = nr.NR_TF_LOG, 1e-7
+    theta = np.concatenate([template.ravel(), [1.0, 1e-7]])
+    mu = np.zeros(P)
+    for p in np.flatnonzero(kind):
+        t = theta[p]
+        mu[p] = {nr.NR_TF_AFFINE: lambda: (t - a[p]) / b[p],
+                 nr.NR_TF_LOG: lambda: np.log((t - a[p]) / b[p]),
+                 nr.NR_TF_LOGIT: lambda: np.log((t - a[p]) / (b[p] - t))}[int(kind[p])]()
+    vi = nr.MvnVI(prob, R, S, kind, a, b, theta, mu=np.tile(mu, (R, 1)), sigma0=0.1, lr=0.05,
+                  seed=2509)
+    graph = vi.graph(n_steps=10)
+    dt = _timed(graph.launch, reps) / 10
+    graph.close()
+    vi.close()
+    return {"what": f"{R} restarts x {S} draws, {L} layers x 300 Q, 5% dQ/Q: full-rank Gaussian "
+                    "VI, one Adam step (draws, logL + gradient, ELBO gradient, Adam), HIP graph",
+            "ms_per_step": dt * 1e3, "value": batch.layer_steps() / dt, "unit": UNIT}
+
+
 def vi_row(nr, reps=5):
     """8192 mean-field VI samples x 20 layers x 1000 Q, 5% dQ/Q: sampler,
     logL + gradient per sample, and the ELBO gradient reduction."""
@@ -514,7 +610,8 @@ def vi_row(nr, reps=5):
 def other_workloads(nr):
     return {"single_film": single_film_row(nr), "cofit": cofit_row(nr),
             "ragged_hmc_f64": ragged_hmc_row(nr, nr.NR_F64),
-            "ragged_hmc_f32": ragged_hmc_row(nr, nr.NR_F32), "vi": vi_row(nr)}
+            "ragged_hmc_f32": ragged_hmc_row(nr, nr.NR_F32), "hmc_driver": hmc_driver_row(nr),
+            "vi": vi_row(nr), "vi_mvn": vi_mvn_row(nr), "deep_stack": deep_stack_row(nr)}
 
 
 def plain_unbatched_row(nr, batch, n_items=64):

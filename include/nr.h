@@ -29,7 +29,7 @@
  *     doubles per row: [thickness d (A), SLD rho_re (A^-2, absolute), imaginary
  *     SLD rho_im (A^-2), roughness sigma (A) of the interface above the row]);
  *     row 0 = fronting (only rho_re is read), the last row = backing (d is not
- *     read); L = rows - 2 finite layers, 0 <= L <= NR_MAX_LAYERS.  The item
+ *     read); L = rows - 2 finite layers, 0 <= L <= NR_MAX_DEEP_LAYERS.  The item
  *     reads dataset dataset_of_item[b], scale[b], bkg[b].
  *   Gradient rows are packed exactly like `layers`; entries the model does not
  *     read are written as 0.  Per item g_inst[2b] = d/dscale, g_inst[2b+1] =
@@ -60,6 +60,11 @@ extern "C" {
 #define NR_VERSION 1
 /* Largest number of finite layers one item may have. */
 #define NR_MAX_LAYERS 40
+/* Items deeper than NR_MAX_LAYERS (up to NR_MAX_DEEP_LAYERS, e.g. microsliced
+ * SLD profiles) are accepted: their value kernels are the same; their gradient
+ * uses the parallel-in-layers scan (layer product split across the 64 lanes
+ * of a wave, one wave per data point), computed in FP64 in both precisions. */
+#define NR_MAX_DEEP_LAYERS 2047
 /* Number of quadrature nodes per data point when dq_over_q > 0. */
 #define NR_SMEAR_NODES 17
 
@@ -97,7 +102,7 @@ typedef struct nr_batch_desc {
   const double* dq_over_q;        /* host [n_datasets], >= 0 and finite */
   int32_t n_items;
   const int32_t* dataset_of_item; /* host [n_items], each in [0, n_datasets) */
-  const int64_t* row_off;         /* host [n_items + 1], row_off[0] = 0, 2 <= rows <= NR_MAX_LAYERS + 2 */
+  const int64_t* row_off;         /* host [n_items + 1], row_off[0] = 0, 2 <= rows <= NR_MAX_DEEP_LAYERS + 2 */
   int32_t precision;              /* NR_F64 or NR_F32 */
 } nr_batch_desc;
 
@@ -110,6 +115,16 @@ typedef struct nr_values {
   const double* scale;  /* [n_items] */
   const double* bkg;    /* [n_items] */
   int32_t* item_status; /* optional [n_items]; NULL to skip; bits are OR-ed in */
+  /* Resolution (Sec. 3 pointwise Gaussian smearing; Sec. 4.1 per-point FWHM;
+   * Sec. 4.2 smearing size as a parameter).  Only datasets with
+   * dq_over_q > 0 are smeared; for them:
+   *   dq        optional [q_off[n_datasets]]: per-point FWHM (A^-1, absolute);
+   *             the nodes of point i are Q_i + (dq_i / (2 sqrt(2 ln 2))) t_k;
+   *   dqq_item  optional [n_items]: the item's relative FWHM dQ/Q, replacing
+   *             the dataset's (used when dq is NULL).
+   * NULL for both: (dQ/Q of the dataset) * Q_i. */
+  const double* dq;
+  const double* dqq_item;
 } nr_values;
 
 /* Operation selector for nr_workspace_size. */
@@ -208,6 +223,16 @@ nr_status nr_loglik_grad(const nr_plan* plan, const nr_values* v, double* logL,
                          double* g_rows, double* g_inst, void* workspace,
                          size_t workspace_bytes, void* stream);
 
+/* nr_loglik_grad plus the derivative of logL with respect to the relative
+ * resolution (Sec. 4.2: the smearing size inferred as a parameter):
+ * g_res[b] = dlogL_b / d(dQ/Q)_b (device [n_items]), through the positions
+ * of the quadrature nodes q_ik = Q_i (1 + (dQ/Q) t_k / (2 sqrt(2 ln 2))).
+ * 0 for items on unsmeared datasets and for all items when values->dq (fixed
+ * per-point widths) is given.  Same workspace and status bits. */
+nr_status nr_loglik_grad_res(const nr_plan* plan, const nr_values* v, double* logL,
+                             double* g_rows, double* g_inst, double* g_res, void* workspace,
+                             size_t workspace_bytes, void* stream);
+
 /* Vector-Jacobian product of R_hat (the autograd of nr_reflectivity): for
  * per-point seeds v (device, packed like R_hat, see nr_output_offsets) writes
  * per item b
@@ -270,6 +295,166 @@ nr_status nr_graph_launch(nr_graph* graph, void* stream);
 
 /* Releases a graph.  NULL is accepted. */
 nr_status nr_graph_destroy(nr_graph* graph);
+
+/* ---------------------------------------------------------------------------
+ * HMC driver around the leapfrog (Sec. 2.3): per chain, a momentum draw
+ * r ~ N(0, M), n_leapfrog leapfrog steps and the Metropolis-Hastings accept
+ * alpha = min{1, exp(H(z, r) - H(z', r'))}, in unconstrained coordinates z
+ * with potential U(z) = -logL(theta(z)) - sum_p ln|dtheta_p/dz_p| (flat
+ * priors) and H = U + r^T M^-1 r / 2, M diagonal.  Each plan item is one
+ * chain.  Random numbers come from Philox4x64-10 (Salmon et al., SC'11) with
+ * key (seed, 0) and counter (iteration, chain, entry / 4, purpose): Box-Muller
+ * normals for the momenta (purpose 0), one uniform for the accept (purpose 1);
+ * a 64-bit output x gives ((x >> 11) + 1/2) 2^-53.  Every chain keeps its own
+ * iteration counter on the device, so replays of a captured transition draw
+ * fresh numbers.
+ * ------------------------------------------------------------------------- */
+
+/* Per-entry transform theta(z) (Sec. 2.3: pre-scaling, sampling in log space,
+ * hard constraints); a and b are the entry's two constants. */
+#define NR_TF_FIXED 0  /* not sampled: theta keeps its value, momentum 0 */
+#define NR_TF_AFFINE 1 /* theta = a + b z */
+#define NR_TF_LOG 2    /* theta = a + b exp(z), b > 0 */
+#define NR_TF_LOGIT 3  /* theta = a + (b - a) / (1 + exp(-z)), a < b */
+
+typedef struct nr_hmc_config {
+  int32_t n_leapfrog;      /* leapfrog steps per transition, >= 1 */
+  double max_energy_error; /* H' - H above this (or NaN) is divergent: rejected, alpha 0 */
+  uint64_t seed;           /* generator key */
+  double target_accept;    /* dual-averaging target, in (0, 1) */
+} nr_hmc_config;
+
+/* The chains' arrays (all DEVICE pointers).  Entries are packed like the rows
+ * (4 per row) and the instrument pairs [scale, bkg] per item.  Entries the
+ * model does not read (fronting d, sigma, rho_im; backing d) are never moved,
+ * whatever their kind. */
+typedef struct nr_hmc_chains {
+  double* z_rows;             /* [rows * 4] unconstrained positions (in/out) */
+  double* z_inst;             /* [2 * n_items] */
+  const uint8_t* kind_rows;   /* [rows * 4] NR_TF_* */
+  const uint8_t* kind_inst;   /* [2 * n_items] */
+  const double* a_rows;       /* transform constants, same layouts */
+  const double* b_rows;
+  const double* a_inst;
+  const double* b_inst;
+  double* inv_mass_rows;      /* diagonal of M^-1 (in; written at a mass window end) */
+  double* inv_mass_inst;
+  double* step;               /* [n_items] leapfrog step per chain (in; adapted) */
+  double* layers;             /* theta: the parameter arrays of nr_values (written on
+                                 moving entries; FIXED entries keep the caller's value) */
+  double* scale;
+  double* bkg;
+  double* logL;               /* [n_items] at theta (written) */
+  double* g_rows;             /* gradient of logL at theta (written) */
+  double* g_inst;
+  double* potential;          /* [n_items] U(z) (written) */
+  double* accept_prob;        /* [n_items] alpha of the last transition */
+  double* energy_error;       /* [n_items] H' - H of the last transition */
+  int32_t* n_accept;          /* [n_items] incremented per accepted transition */
+  int32_t* n_divergent;       /* [n_items] incremented per divergent transition */
+} nr_hmc_chains;
+
+typedef struct nr_hmc nr_hmc;
+
+/* Driver state for the plan's items as chains: momenta, the saved state of a
+ * transition, Welford sums and dual-averaging state; iteration counters and
+ * adaptation state start at zero.  Allocates device memory (not capturable).
+ * The plan must outlive the driver. */
+nr_status nr_hmc_create(const nr_plan* plan, const nr_hmc_config* cfg, nr_hmc** out);
+nr_status nr_hmc_destroy(nr_hmc* hmc);
+
+/* Evaluates the chains at their positions: theta = theta(z) (with from_theta
+ * != 0, z = theta^-1(theta) first), logL and its gradient, U.  Needed before
+ * the first transition and after the caller changes z or theta.  `data` gives
+ * q, r_obs, r_err (and optional status, resolution); its parameter pointers
+ * are ignored.  Uses the NR_OP_LOGLIK_GRAD workspace. */
+nr_status nr_hmc_init(nr_hmc* hmc, const nr_values* data, const nr_hmc_chains* ch,
+                      int32_t from_theta, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Adaptation during a transition (bits): */
+#define NR_HMC_ADAPT_MASS 1 /* push the post-transition z into the Welford window */
+#define NR_HMC_ADAPT_STEP 2 /* dual averaging of the step (Hoffman and Gelman 2014,
+                               gamma 0.05, t0 10, kappa 0.75) toward target_accept */
+
+/* One transition of every chain.  Same arguments as nr_hmc_init. */
+nr_status nr_hmc_transition(nr_hmc* hmc, const nr_values* data, const nr_hmc_chains* ch,
+                            int32_t adapt, void* workspace, size_t workspace_bytes,
+                            void* stream);
+
+/* Captures n_transitions transitions into a HIP graph (every pointer baked
+ * in; see nr_leapfrog_graph_create).  Replays continue the chains. */
+nr_status nr_hmc_graph_create(nr_hmc* hmc, const nr_values* data, const nr_hmc_chains* ch,
+                              int32_t adapt, int32_t n_transitions, void* workspace,
+                              size_t workspace_bytes, nr_graph** graph_out);
+
+/* Warm-up controls between transitions (bits): */
+#define NR_HMC_MASS_WINDOW_END 1 /* inverse mass = (n/(n+5)) var + 1e-3 (5/(n+5)) of the
+                                    window's positions (n >= 2), window restarts */
+#define NR_HMC_STEP_RESTART 2    /* dual averaging restarts at mu = ln(10 step) */
+#define NR_HMC_STEP_FINAL 4      /* step = the dual average exp(log eps_bar) */
+nr_status nr_hmc_adapt(nr_hmc* hmc, const nr_hmc_chains* ch, int32_t actions, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Full-rank Gaussian variational fit (Sec. 2.4 VI; Sec. 4.2: a multivariate
+ * normal surrogate in unconstrained space, Adam, independent restarts, the
+ * best ELBO kept).  The plan's items are R restarts x S draws (item r S + s),
+ * all with the same number of rows; entry p of a draw is row entry p (4 per
+ * row), then scale, bkg (P = 4 rows + 2).  Per restart,
+ *   z = mu + L eps, eps ~ N(0, I), theta = theta(z) (the NR_TF_* transforms),
+ *   L lower triangular, L_ii = softplus(omega_i), L_ij = lambda_ij (i > j),
+ *   ELBO = E[logL(theta(z)) + sum ln|dtheta/dz|] + sum ln L_ii + (n/2) ln(2 pi e)
+ * over the n moving entries (transform other than FIXED, read by the model);
+ * flat priors.  Draws: Philox4x64-10, counter (iteration, item, entry / 4, 2)
+ * (see the HMC driver).  Gradients (h_s = z-gradient of the log target):
+ *   dmu_i = mean_s h_si; dlambda_ij = mean_s h_si eps_sj;
+ *   domega_i = (mean_s h_si eps_si + 1/L_ii) sigmoid(omega_i).
+ * Adam (Kingma and Ba 2015): x += lr mhat / (sqrt(vhat) + eps), ascending.
+ * ------------------------------------------------------------------------- */
+typedef struct nr_vi_mvn_config {
+  int32_t n_restarts; /* R >= 1 */
+  int32_t n_draws;    /* S >= 1 draws per restart and step */
+  double lr;          /* Adam step (Sec. 4.2: 0.05) */
+  double beta1;       /* Adam moment decays and floor (0.9, 0.999, 1e-8) */
+  double beta2;
+  double adam_eps;
+  uint64_t seed;
+} nr_vi_mvn_config;
+
+/* Variational parameters and outputs (all DEVICE pointers). */
+typedef struct nr_vi_mvn_params {
+  const uint8_t* kind;        /* [P] NR_TF_* per entry, shared by the restarts */
+  const double* a;            /* [P] transform constants */
+  const double* b;            /* [P] */
+  const double* theta_fixed;  /* [P] theta of the entries that do not move */
+  double* mu;                 /* [R * P] */
+  double* omega;              /* [R * P] */
+  double* lam;                /* [R * P * P] row-major; row i, columns j < i are lambda_ij */
+  double* elbo;               /* [R] estimate at the step's draws (written) */
+  double* grad_mu;            /* [R * P] (written; 0 on entries that do not move) */
+  double* grad_omega;         /* [R * P] */
+  double* grad_lam;           /* [R * P * P] (written; 0 outside j < i) */
+} nr_vi_mvn_params;
+
+typedef struct nr_vi_mvn nr_vi_mvn;
+
+/* Driver state for the plan (R x S items, equal rows): the draws, the draws'
+ * parameters, logL and gradient, and the Adam moments (zero), iteration 0.
+ * Allocates device memory (not capturable).  The plan must outlive it. */
+nr_status nr_vi_mvn_create(const nr_plan* plan, const nr_vi_mvn_config* cfg, nr_vi_mvn** out);
+nr_status nr_vi_mvn_destroy(nr_vi_mvn* vi);
+
+/* One step: draws for the current iteration, the ELBO estimate and its
+ * gradient per restart; with adam != 0, one Adam step of mu, omega and lambda
+ * on moving entries.  The iteration advances.  `data` gives q, r_obs, r_err
+ * (its parameter pointers are ignored).  Uses the NR_OP_LOGLIK_GRAD
+ * workspace. */
+nr_status nr_vi_mvn_step(nr_vi_mvn* vi, const nr_values* data, const nr_vi_mvn_params* prm,
+                         int32_t adam, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Captures n_steps steps (with Adam) into a HIP graph; replays continue. */
+nr_status nr_vi_mvn_graph_create(nr_vi_mvn* vi, const nr_values* data,
+                                 const nr_vi_mvn_params* prm, int32_t n_steps, void* workspace,
+                                 size_t workspace_bytes, nr_graph** graph_out);
 
 /* Reparameterised Monte-Carlo gradient of the evidence lower bound for a
  * mean-field Gaussian q (Sec. 2.4, Monte-Carlo estimate of the loss and of its

@@ -86,6 +86,12 @@ def accept_uniform(seed, iteration, chain):
     return open_uniform(philox4x64((iteration, chain, 0, 1), (seed, 0))[0])
 
 
+def _exp(x):
+    """exp that overflows to inf (a runaway trajectory must reach the
+    divergence rule, not raise)."""
+    return math.exp(x) if x < 709.0 else math.inf
+
+
 def _sigmoid(z):
     return 1.0 / (1.0 + math.exp(-z)) if z >= 0 else math.exp(z) / (1.0 + math.exp(z))
 
@@ -99,7 +105,7 @@ def transform(kind, a, b, z):
     if kind == AFFINE:
         return a + b * z, b, math.log(abs(b)), 0.0
     if kind == LOG:
-        ez = math.exp(z)
+        ez = _exp(z)
         return a + b * ez, b * ez, math.log(b) + z, 1.0
     if kind == LOGIT:
         s = _sigmoid(z)
@@ -189,7 +195,7 @@ class Chain:
         H1 = self.U + 0.5 * np.sum(self.inv_mass[live] * r[live] ** 2)
         delta = H1 - H0
         divergent = not (delta <= max_error)
-        alpha = 0.0 if divergent else min(1.0, math.exp(-delta))
+        alpha = 0.0 if divergent else min(1.0, _exp(-delta))
         u = accept_uniform(self.seed, self.iteration, self.chain_id)
         accept = u < alpha
         if not accept:

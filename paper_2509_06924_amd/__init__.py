@@ -19,11 +19,14 @@ from . import _native as _n
 from ._native import (NR_F32, NR_F64, NR_ITEM_BAD_ERR, NR_ITEM_BAD_Q,  # noqa: F401
                       NR_ITEM_EDGE_SINGULAR,
                       NR_ITEM_NONFINITE, NR_MAX_LAYERS, NR_OP_LOGLIK,
-                      NR_OP_LOGLIK_GRAD, NR_OP_REFLECTIVITY, NativeError)
+                      NR_OP_LOGLIK_GRAD, NR_OP_REFLECTIVITY, NativeError,
+                      NR_TF_FIXED, NR_TF_AFFINE, NR_TF_LOG, NR_TF_LOGIT,
+                      NR_HMC_ADAPT_MASS, NR_HMC_ADAPT_STEP, NR_HMC_MASS_WINDOW_END,
+                      NR_HMC_STEP_RESTART, NR_HMC_STEP_FINAL)
 
 __all__ = ["Plan", "Problem", "plan_options", "bucket_lmax", "NRLogLik", "NRReflectivity",
            "nr_reflectivity", "nr_loglik", "nr_loglik_grad", "pack_theta", "NativeError",
-           "HmcState", "LeapfrogGraph", "tie_sum", "tie_map_to_csr"]
+           "HmcState", "LeapfrogGraph", "HMC", "MvnVI", "tie_sum", "tie_map_to_csr"]
 
 
 def _ptr(a):
@@ -114,9 +117,9 @@ def _dp(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def _values(q, r_obs, r_err, layers, scale, bkg, item_status=None):
+def _values(q, r_obs, r_err, layers, scale, bkg, item_status=None, dq=None, dqq_item=None):
     return _n.Values(_dp(q), _dp(r_obs), _dp(r_err), _dp(layers), _dp(scale), _dp(bkg),
-                     _dp(item_status))
+                     _dp(item_status), _dp(dq), _dp(dqq_item))
 
 
 def _stream(stream):
@@ -162,6 +165,8 @@ class Problem:
         self.scale = torch.as_tensor(scale, **f).contiguous()
         self.bkg = torch.as_tensor(bkg, **f).contiguous()
         self.item_status = torch.zeros(plan.n_items, dtype=torch.int32, device=self.device)
+        self.dq = None        # per-point FWHM (packed like q), smeared datasets
+        self.dqq_item = None  # per-item relative FWHM dQ/Q
         self._ws = {}
         self.out_off = plan.output_offsets()
 
@@ -180,6 +185,23 @@ class Problem:
                                        device=self.device)
         return self._ws[op]
 
+    def set_resolution(self, dq=None, dqq_item=None):
+        """Resolution of the smeared datasets (those with dq_over_q > 0):
+        per-point FWHM widths `dq` (1/A, packed like q), or a relative width
+        dQ/Q per item `dqq_item`; None restores the dataset's dQ/Q."""
+        import torch
+        f = dict(dtype=torch.float64, device=self.device)
+        if dq is not None:
+            dq = torch.as_tensor(dq, **f).reshape(-1).contiguous()
+            if dq.numel() != self.q.numel():
+                raise ValueError("dq must hold one width per data point")
+        if dqq_item is not None:
+            dqq_item = torch.as_tensor(dqq_item, **f).reshape(-1).contiguous()
+            if dqq_item.numel() != self.plan.n_items:
+                raise ValueError("dqq_item must hold one value per item")
+        self.dq, self.dqq_item = dq, dqq_item
+        return self
+
     def values(self, layers=None, scale=None, bkg=None):
         layers = self.layers if layers is None else layers
         scale = self.scale if scale is None else scale
@@ -190,7 +212,8 @@ class Problem:
         if layers.numel() != self.layers.numel() or scale.numel() != self.plan.n_items \
                 or bkg.numel() != self.plan.n_items:
             raise ValueError("parameter sizes do not match the plan")
-        return _values(self.q, self.r_obs, self.r_err, layers, scale, bkg, self.item_status)
+        return _values(self.q, self.r_obs, self.r_err, layers, scale, bkg, self.item_status,
+                       self.dq, self.dqq_item)
 
     def reflectivity(self, layers=None, scale=None, bkg=None, stream=None):
         import torch
@@ -216,6 +239,20 @@ class Problem:
         nr_loglik_grad(self.plan, self.values(layers, scale, bkg), logL, g_rows, g_inst,
                        self.workspace(NR_OP_LOGLIK_GRAD), stream)
         return logL, g_rows, g_inst
+
+    def loglik_grad_res(self, layers=None, scale=None, bkg=None, stream=None):
+        """loglik_grad plus g_res[b] = dlogL_b/d(dQ/Q)_b (0 on unsmeared
+        datasets and with per-point widths)."""
+        import torch
+        logL = torch.empty(self.plan.n_items, dtype=torch.float64, device=self.device)
+        g_rows = torch.empty_like(self.layers)
+        g_inst = torch.empty(self.plan.n_items, 2, dtype=torch.float64, device=self.device)
+        g_res = torch.empty(self.plan.n_items, dtype=torch.float64, device=self.device)
+        ws = self.workspace(NR_OP_LOGLIK_GRAD)
+        _n.check(_n.lib().nr_loglik_grad_res(
+            self.plan.handle, ctypes.byref(self.values(layers, scale, bkg)), _dp(logL),
+            _dp(g_rows), _dp(g_inst), _dp(g_res), _dp(ws), ws.numel() * 8, _stream(stream)))
+        return logL, g_rows, g_inst, g_res
 
 
 def _reflectivity_vjp(self, seed, layers=None, scale=None, bkg=None, stream=None):
@@ -285,6 +322,212 @@ class LeapfrogGraph:
     def close(self):
         if getattr(self, "_h", None):
             _n.lib().nr_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Graph:
+    """A captured HIP graph (nr_graph); launch() replays it."""
+
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep  # objects whose device pointers the graph holds
+
+    def launch(self, stream=None):
+        _n.check(_n.lib().nr_graph_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _n.lib().nr_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HMC:
+    """HMC driver (nr_hmc_*): the problem's items are independent chains.
+
+    Per entry (rows as (R, 4), instrument as (n, 2) [scale, bkg]): the
+    transform kind (NR_TF_*), its constants a and b, and the diagonal inverse
+    mass; per chain the leapfrog step.  The chain starts at the problem's
+    parameters (z from theta on init).  Device tensors after each call:
+    z_rows/z_inst, layers/scale/bkg (theta), logL, g_rows, g_inst, potential,
+    accept_prob, energy_error, n_accept, n_divergent, inv_mass_*, step."""
+
+    def __init__(self, problem, kind_rows=None, kind_inst=None, a_rows=None, b_rows=None,
+                 a_inst=None, b_inst=None, inv_mass_rows=None, inv_mass_inst=None, step=0.01,
+                 n_leapfrog=10, max_energy_error=1000.0, seed=0, target_accept=0.8):
+        import torch
+        self.problem = problem
+        dev = problem.device
+        n = problem.plan.n_items
+        R = problem.layers.shape[0]
+        f = dict(dtype=torch.float64, device=dev)
+
+        def arr(v, shape, default, dtype=torch.float64):
+            if v is None:
+                return torch.full(shape, default, dtype=dtype, device=dev)
+            return torch.as_tensor(v, dtype=dtype, device=dev).reshape(shape).contiguous().clone()
+
+        self.kind_rows = arr(kind_rows, (R, 4), NR_TF_AFFINE, torch.uint8)
+        self.kind_inst = arr(kind_inst, (n, 2), NR_TF_AFFINE, torch.uint8)
+        self.a_rows = arr(a_rows, (R, 4), 0.0)
+        self.b_rows = arr(b_rows, (R, 4), 1.0)
+        self.a_inst = arr(a_inst, (n, 2), 0.0)
+        self.b_inst = arr(b_inst, (n, 2), 1.0)
+        self.inv_mass_rows = arr(inv_mass_rows, (R, 4), 1.0)
+        self.inv_mass_inst = arr(inv_mass_inst, (n, 2), 1.0)
+        self.step = (torch.full((n,), float(step), **f) if np.ndim(step) == 0
+                     else arr(step, (n,), 0.0))
+        self.layers = problem.layers.clone()
+        self.scale = problem.scale.clone()
+        self.bkg = problem.bkg.clone()
+        self.z_rows = torch.zeros(R, 4, **f)
+        self.z_inst = torch.zeros(n, 2, **f)
+        self.logL = torch.zeros(n, **f)
+        self.g_rows = torch.zeros(R, 4, **f)
+        self.g_inst = torch.zeros(n, 2, **f)
+        self.potential = torch.zeros(n, **f)
+        self.accept_prob = torch.zeros(n, **f)
+        self.energy_error = torch.zeros(n, **f)
+        self.n_accept = torch.zeros(n, dtype=torch.int32, device=dev)
+        self.n_divergent = torch.zeros(n, dtype=torch.int32, device=dev)
+        self.config = _n.HmcConfig(int(n_leapfrog), float(max_energy_error), int(seed),
+                                   float(target_accept))
+        h = ctypes.c_void_p()
+        _n.check(_n.lib().nr_hmc_create(problem.plan.handle, ctypes.byref(self.config),
+                                        ctypes.byref(h)))
+        self._h = h
+        self._chains = _n.HmcChains(*[_dp(t) for t in (
+            self.z_rows, self.z_inst, self.kind_rows, self.kind_inst, self.a_rows, self.b_rows,
+            self.a_inst, self.b_inst, self.inv_mass_rows, self.inv_mass_inst, self.step,
+            self.layers, self.scale, self.bkg, self.logL, self.g_rows, self.g_inst,
+            self.potential, self.accept_prob, self.energy_error, self.n_accept,
+            self.n_divergent)])
+        self._data = problem.values()
+
+    def _ws(self):
+        ws = self.problem.workspace(NR_OP_LOGLIK_GRAD)
+        return _dp(ws), ws.numel() * 8
+
+    def init(self, from_theta=True, stream=None):
+        ws, nb = self._ws()
+        _n.check(_n.lib().nr_hmc_init(self._h, ctypes.byref(self._data),
+                                      ctypes.byref(self._chains), int(bool(from_theta)), ws, nb,
+                                      _stream(stream)))
+        return self
+
+    @staticmethod
+    def _adapt_bits(adapt_mass, adapt_step):
+        return (NR_HMC_ADAPT_MASS if adapt_mass else 0) | (NR_HMC_ADAPT_STEP if adapt_step else 0)
+
+    def transition(self, adapt_mass=False, adapt_step=False, stream=None):
+        ws, nb = self._ws()
+        _n.check(_n.lib().nr_hmc_transition(self._h, ctypes.byref(self._data),
+                                            ctypes.byref(self._chains),
+                                            self._adapt_bits(adapt_mass, adapt_step), ws, nb,
+                                            _stream(stream)))
+
+    def graph(self, n_transitions=1, adapt_mass=False, adapt_step=False):
+        ws, nb = self._ws()
+        g = ctypes.c_void_p()
+        _n.check(_n.lib().nr_hmc_graph_create(self._h, ctypes.byref(self._data),
+                                              ctypes.byref(self._chains),
+                                              self._adapt_bits(adapt_mass, adapt_step),
+                                              int(n_transitions), ws, nb, ctypes.byref(g)))
+        return _Graph(g, self)
+
+    def adapt(self, mass_window_end=False, step_restart=False, step_final=False, stream=None):
+        bits = ((NR_HMC_MASS_WINDOW_END if mass_window_end else 0)
+                | (NR_HMC_STEP_RESTART if step_restart else 0)
+                | (NR_HMC_STEP_FINAL if step_final else 0))
+        _n.check(_n.lib().nr_hmc_adapt(self._h, ctypes.byref(self._chains), bits,
+                                       _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _n.lib().nr_hmc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MvnVI:
+    """Full-rank Gaussian VI driver (nr_vi_mvn_*): `problem` has R x S items
+    (restart r, draw s at item r S + s) with equal rows.  Per entry (P =
+    4 rows + 2: the rows, then scale, bkg) the transform kind and constants
+    and the value of entries that do not move; per restart mu (default from
+    the inverse transform of theta_fixed), omega = softplus^-1(sigma0) and
+    lambda = 0.  Device tensors: mu (R, P), omega (R, P), lam (R, P, P),
+    elbo (R,), grad_mu, grad_omega, grad_lam."""
+
+    def __init__(self, problem, n_restarts, n_draws, kind, a, b, theta_fixed, mu=None,
+                 sigma0=0.1, lr=0.05, beta1=0.9, beta2=0.999, adam_eps=1e-8, seed=0):
+        import torch
+        dev = problem.device
+        f = dict(dtype=torch.float64, device=dev)
+        R, S = int(n_restarts), int(n_draws)
+        self.problem = problem
+        self.kind = torch.as_tensor(kind, dtype=torch.uint8, device=dev).reshape(-1).contiguous()
+        P = self.kind.numel()
+        self.a = torch.as_tensor(a, **f).reshape(P).contiguous()
+        self.b = torch.as_tensor(b, **f).reshape(P).contiguous()
+        self.theta_fixed = torch.as_tensor(theta_fixed, **f).reshape(P).contiguous()
+        if mu is None:
+            raise ValueError("mu (R x P, unconstrained) is required")
+        self.mu = torch.as_tensor(mu, **f).reshape(R, P).contiguous().clone()
+        w = float(sigma0 + np.log(-np.expm1(-sigma0)))
+        self.omega = torch.full((R, P), w, **f)
+        self.lam = torch.zeros(R, P, P, **f)
+        self.elbo = torch.zeros(R, **f)
+        self.grad_mu = torch.zeros(R, P, **f)
+        self.grad_omega = torch.zeros(R, P, **f)
+        self.grad_lam = torch.zeros(R, P, P, **f)
+        self.config = _n.MvnConfig(R, S, float(lr), float(beta1), float(beta2), float(adam_eps),
+                                   int(seed))
+        h = ctypes.c_void_p()
+        _n.check(_n.lib().nr_vi_mvn_create(problem.plan.handle, ctypes.byref(self.config),
+                                           ctypes.byref(h)))
+        self._h = h
+        self._prm = _n.MvnParams(*[_dp(t) for t in (
+            self.kind, self.a, self.b, self.theta_fixed, self.mu, self.omega, self.lam,
+            self.elbo, self.grad_mu, self.grad_omega, self.grad_lam)])
+        self._data = problem.values()
+
+    def _ws(self):
+        ws = self.problem.workspace(NR_OP_LOGLIK_GRAD)
+        return _dp(ws), ws.numel() * 8
+
+    def step(self, adam=True, stream=None):
+        ws, nb = self._ws()
+        _n.check(_n.lib().nr_vi_mvn_step(self._h, ctypes.byref(self._data),
+                                         ctypes.byref(self._prm), int(bool(adam)), ws, nb,
+                                         _stream(stream)))
+
+    def graph(self, n_steps=1):
+        ws, nb = self._ws()
+        g = ctypes.c_void_p()
+        _n.check(_n.lib().nr_vi_mvn_graph_create(self._h, ctypes.byref(self._data),
+                                                 ctypes.byref(self._prm), int(n_steps), ws, nb,
+                                                 ctypes.byref(g)))
+        return _Graph(g, self)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _n.lib().nr_vi_mvn_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -12,9 +12,13 @@ NR_F64, NR_F32 = 0, 1
 NR_OP_REFLECTIVITY, NR_OP_LOGLIK, NR_OP_LOGLIK_GRAD = 0, 1, 2
 NR_ITEM_NONFINITE, NR_ITEM_BAD_Q, NR_ITEM_BAD_ERR, NR_ITEM_EDGE_SINGULAR = 1, 2, 4, 8
 NR_MAX_LAYERS = 40
+NR_MAX_DEEP_LAYERS = 2047
 NR_SMEAR_NODES = 17
 NR_NUM_BUCKETS = 16
 NR_VARIANT_AUTO, NR_VARIANT_STORE, NR_VARIANT_RECOMPUTE = 0, 1, 2
+NR_TF_FIXED, NR_TF_AFFINE, NR_TF_LOG, NR_TF_LOGIT = 0, 1, 2, 3
+NR_HMC_ADAPT_MASS, NR_HMC_ADAPT_STEP = 1, 2
+NR_HMC_MASS_WINDOW_END, NR_HMC_STEP_RESTART, NR_HMC_STEP_FINAL = 1, 2, 4
 
 # every symbol include/nr.h declares
 EXPORTS = ("nr_version", "nr_status_string", "nr_plan_create", "nr_plan_destroy",
@@ -22,7 +26,10 @@ EXPORTS = ("nr_version", "nr_status_string", "nr_plan_create", "nr_plan_destroy"
            "nr_loglik_grad", "nr_plan_set_timing_events", "nr_leapfrog",
            "nr_leapfrog_graph_create", "nr_graph_launch", "nr_graph_destroy",
            "nr_vi_elbo_grad", "nr_tie_sum", "nr_plan_options_default", "nr_bucket_lmax",
-           "nr_store_max_layers", "nr_plan_create_ex", "nr_reflectivity_vjp")
+           "nr_store_max_layers", "nr_plan_create_ex", "nr_reflectivity_vjp",
+           "nr_loglik_grad_res", "nr_hmc_create", "nr_hmc_destroy", "nr_hmc_init",
+           "nr_hmc_transition", "nr_hmc_graph_create", "nr_hmc_adapt", "nr_vi_mvn_create",
+           "nr_vi_mvn_destroy", "nr_vi_mvn_step", "nr_vi_mvn_graph_create")
 
 
 class BatchDesc(ctypes.Structure):
@@ -54,6 +61,8 @@ class Values(ctypes.Structure):
         ("scale", ctypes.c_void_p),
         ("bkg", ctypes.c_void_p),
         ("item_status", ctypes.c_void_p),
+        ("dq", ctypes.c_void_p),
+        ("dqq_item", ctypes.c_void_p),
     ]
 
 
@@ -61,6 +70,40 @@ class HmcState(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in (
         "layers", "scale", "bkg", "mom_rows", "mom_inst", "inv_mass_rows", "inv_mass_inst",
         "logL", "g_rows", "g_inst")]
+
+
+class HmcConfig(ctypes.Structure):
+    _fields_ = [
+        ("n_leapfrog", ctypes.c_int32),
+        ("max_energy_error", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("target_accept", ctypes.c_double),
+    ]
+
+
+class HmcChains(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in (
+        "z_rows", "z_inst", "kind_rows", "kind_inst", "a_rows", "b_rows", "a_inst", "b_inst",
+        "inv_mass_rows", "inv_mass_inst", "step", "layers", "scale", "bkg", "logL", "g_rows",
+        "g_inst", "potential", "accept_prob", "energy_error", "n_accept", "n_divergent")]
+
+
+class MvnConfig(ctypes.Structure):
+    _fields_ = [
+        ("n_restarts", ctypes.c_int32),
+        ("n_draws", ctypes.c_int32),
+        ("lr", ctypes.c_double),
+        ("beta1", ctypes.c_double),
+        ("beta2", ctypes.c_double),
+        ("adam_eps", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class MvnParams(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in (
+        "kind", "a", "b", "theta_fixed", "mu", "omega", "lam", "elbo", "grad_mu", "grad_omega",
+        "grad_lam")]
 
 
 class ViArgs(ctypes.Structure):
@@ -114,6 +157,9 @@ def lib():
         L.nr_loglik.argtypes = [P, ctypes.POINTER(Values), P, P, ctypes.c_size_t, P]
         L.nr_loglik_grad.restype = ctypes.c_int32
         L.nr_loglik_grad.argtypes = [P, ctypes.POINTER(Values), P, P, P, P, ctypes.c_size_t, P]
+        L.nr_loglik_grad_res.restype = ctypes.c_int32
+        L.nr_loglik_grad_res.argtypes = [P, ctypes.POINTER(Values), P, P, P, P, P,
+                                         ctypes.c_size_t, P]
         L.nr_reflectivity_vjp.restype = ctypes.c_int32
         L.nr_reflectivity_vjp.argtypes = [P, ctypes.POINTER(Values), P, P, P, P, P,
                                           ctypes.c_size_t, P]
@@ -133,6 +179,33 @@ def lib():
         L.nr_vi_elbo_grad.restype = ctypes.c_int32
         L.nr_vi_elbo_grad.argtypes = [P, ctypes.POINTER(Values), ctypes.POINTER(ViArgs), P,
                                       ctypes.c_size_t, P]
+        L.nr_hmc_create.restype = ctypes.c_int32
+        L.nr_hmc_create.argtypes = [P, ctypes.POINTER(HmcConfig), ctypes.POINTER(P)]
+        L.nr_hmc_destroy.restype = ctypes.c_int32
+        L.nr_hmc_destroy.argtypes = [P]
+        L.nr_hmc_init.restype = ctypes.c_int32
+        L.nr_hmc_init.argtypes = [P, ctypes.POINTER(Values), ctypes.POINTER(HmcChains),
+                                  ctypes.c_int32, P, ctypes.c_size_t, P]
+        L.nr_hmc_transition.restype = ctypes.c_int32
+        L.nr_hmc_transition.argtypes = [P, ctypes.POINTER(Values), ctypes.POINTER(HmcChains),
+                                        ctypes.c_int32, P, ctypes.c_size_t, P]
+        L.nr_hmc_graph_create.restype = ctypes.c_int32
+        L.nr_hmc_graph_create.argtypes = [P, ctypes.POINTER(Values), ctypes.POINTER(HmcChains),
+                                          ctypes.c_int32, ctypes.c_int32, P, ctypes.c_size_t,
+                                          ctypes.POINTER(P)]
+        L.nr_hmc_adapt.restype = ctypes.c_int32
+        L.nr_hmc_adapt.argtypes = [P, ctypes.POINTER(HmcChains), ctypes.c_int32, P]
+        L.nr_vi_mvn_create.restype = ctypes.c_int32
+        L.nr_vi_mvn_create.argtypes = [P, ctypes.POINTER(MvnConfig), ctypes.POINTER(P)]
+        L.nr_vi_mvn_destroy.restype = ctypes.c_int32
+        L.nr_vi_mvn_destroy.argtypes = [P]
+        L.nr_vi_mvn_step.restype = ctypes.c_int32
+        L.nr_vi_mvn_step.argtypes = [P, ctypes.POINTER(Values), ctypes.POINTER(MvnParams),
+                                     ctypes.c_int32, P, ctypes.c_size_t, P]
+        L.nr_vi_mvn_graph_create.restype = ctypes.c_int32
+        L.nr_vi_mvn_graph_create.argtypes = [P, ctypes.POINTER(Values), ctypes.POINTER(MvnParams),
+                                             ctypes.c_int32, P, ctypes.c_size_t,
+                                             ctypes.POINTER(P)]
         L.nr_tie_sum.restype = ctypes.c_int32
         L.nr_tie_sum.argtypes = [ctypes.c_int64, P, P, P, P, P]
         _lib = L

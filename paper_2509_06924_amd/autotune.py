@@ -49,13 +49,17 @@ def structure_key(q_off, row_off, dataset_of_item, precision, device_name=""):
     nq = np.diff(q_off)[dsi] if n else np.zeros(0, np.int64)
     lm = np.array(bucket_lmax())
     b = np.searchsorted(lm, L) if n else np.zeros(0, np.int64)
-    work = (lm[b] + 1) * nq if n else np.zeros(0)
+    # items deeper than the last bucket (the scan kernel) count as their depth
+    depth = np.where(b < lm.size, lm[np.minimum(b, lm.size - 1)], L) if n else np.zeros(0)
+    work = (depth + 1) * nq if n else np.zeros(0)
     tot = float(work.sum()) or 1.0
-    shares = {int(lm[k]): round(float(work[b == k].sum()) / tot, 1) for k in np.unique(b)}
+    shares = {(int(lm[k]) if k < lm.size else "deep"): round(float(work[b == k].sum()) / tot, 1)
+              for k in np.unique(b)}
     mean_nq = float(nq.mean()) if n else 0.0
     return json.dumps({
         "precision": int(precision),
-        "buckets": {str(k): v for k, v in sorted(shares.items()) if v > 0},
+        "buckets": {str(k): v for k, v in sorted(shares.items(), key=lambda kv: str(kv[0]))
+                    if v > 0},
         "log2_points_per_item": int(round(math.log2(mean_nq))) if mean_nq > 0 else 0,
         "log2_items": int(round(math.log2(n))) if n > 0 else 0,
         "device": device_name,
@@ -127,7 +131,7 @@ def tune(batch, precision=_n.NR_F64, device="cuda", cache=None, reps=7, verbose=
 
     lm = bucket_lmax()
     L = np.diff(np.asarray(batch.row_off)) - 2
-    used = sorted(set(int(lm[k]) for k in np.searchsorted(lm, L))) if L.size else []
+    used = sorted(set(int(lm[k]) for k in np.searchsorted(lm, L) if k < len(lm))) if L.size else []
     smax = int(_n.lib().nr_store_max_layers(precision))
     best = {"grad_variant": {}, "xcd_run": 8, "pack_tails": 1}
     best_t = _time_call(problem(best), out, reps)

@@ -93,6 +93,7 @@ struct Launch {
   int bucket = 0;
   bool store = false;  // gradient: store variant (else recompute)
   bool tail = false;
+  int scan_ch = 0;  // deep list: the largest levels-per-lane of its items
   int n_wu = 0;
   int32_t* item = nullptr;      // [n_wu]: the unit's item (first item for tails)
   int32_t* p0 = nullptr;        // [n_wu]: first point (full units)
@@ -157,6 +158,7 @@ struct nr_plan {
   std::vector<Launch> launches_fwd, launches_grad;
   uint8_t* d_row_kind = nullptr;  // 0 fronting, 1 layer, 2 backing, per row
   int uniform_rows = 0;           // rows per item if all items agree, else 0
+  int max_rows = 2;               // rows of the deepest item
   double node_t[kSmearNodes], node_w[kSmearNodes];
   std::vector<void*> owned;
 };
@@ -185,7 +187,7 @@ nr_status validate_desc(const nr_batch_desc* d) {
   }
   for (int b = 0; b < d->n_items; ++b) {
     const int64_t rows = d->row_off[b + 1] - d->row_off[b];
-    if (rows < 2 || rows > NR_MAX_LAYERS + 2) return NR_EINVAL;
+    if (rows < 2 || rows > NR_MAX_DEEP_LAYERS + 2) return NR_EINVAL;
     const int32_t s = d->dataset_of_item[b];
     if (s < 0 || s >= d->n_datasets) return NR_EINVAL;
   }
@@ -220,6 +222,8 @@ KernelArgs base_args(const nr_plan* p, const nr_values* v) {
   a.scale = v->scale;
   a.bkg = v->bkg;
   a.item_status = v->item_status;
+  a.dq = v->dq;
+  a.dqq_item = v->dqq_item;
   a.rule = p->d_rule;
   return a;
 }
@@ -242,9 +246,12 @@ size_t op_doubles(const nr_plan* p, int op) {
 }
 
 nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st,
-                       bool events = true);
+                       bool events = true, bool res = false);
 
-nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st, bool events) {
+// res: gradient launches take the form that also yields the derivative with
+// respect to the relative resolution.
+nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st, bool events,
+                       bool res) {
   {
     hipError_t e = launch_item_consts(p->d_row_off, a.layers, const_cast<double*>(a.consts),
                                       const_cast<float*>(a.constsf), p->n_items, st);
@@ -262,8 +269,14 @@ nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st, b
     a.tail_item = L.lane_item;
     a.tail_pt = L.lane_pt;
     a.tail_rec = L.lane_rec;
-    hipError_t e = grad ? launch_grad(p->precision, L.bucket, L.store, L.tail, a, L.n_wu, st)
-                        : launch_forward(p->precision, op, a, L.n_wu, st);
+    const int form = res ? kFormRecomputeRes : L.store ? kFormStore : kFormRecompute;
+    hipError_t e;
+    if (!grad)
+      e = launch_forward(p->precision, op, a, L.n_wu, st);
+    else if (L.bucket == kDeepBucket)
+      e = launch_grad_scan(res, L.scan_ch, a, L.n_wu, st);
+    else
+      e = launch_grad(p->precision, L.bucket, form, L.tail, a, L.n_wu, st);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
   }
   if (events && p->ev_stop) {
@@ -277,13 +290,13 @@ nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st, b
 // seed set, the vector-Jacobian product of R_hat instead.
 nr_status enqueue_grad(const nr_plan* p, const nr_values* v, double* logL, double* g_rows,
                        double* g_inst, void* ws, hipStream_t s, bool events,
-                       const double* seed = nullptr) {
+                       const double* seed = nullptr, double* g_res = nullptr) {
   KernelArgs a = base_args(p, v);
   a.seed = seed;
   a.consts = static_cast<double*>(ws);
   a.constsf = consts_floats(p, a.consts);
   a.rec = static_cast<double*>(ws) + consts_doubles(p);
-  nr_status st = run_launches(p, kOpLoglikGrad, a, s, events);
+  nr_status st = run_launches(p, kOpLoglikGrad, a, s, events, g_res != nullptr);
   if (st != NR_OK) return st;
   ReduceArgs r;
   std::memset(&r, 0, sizeof(r));
@@ -297,6 +310,8 @@ nr_status enqueue_grad(const nr_plan* p, const nr_values* v, double* logL, doubl
   r.logL = logL;
   r.g_rows = g_rows;
   r.g_inst = g_inst;
+  r.g_res = g_res;
+  r.max_rows = p->max_rows;
   hipError_t e = launch_reduce(kOpLoglikGrad, r, s);
   return e == hipSuccess ? NR_OK : hip_fail(e, "reduce launch");
 }
@@ -349,6 +364,189 @@ struct nr_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
+
+struct nr_hmc {
+  const nr_plan* plan = nullptr;
+  nr_hmc_config cfg;
+  int64_t n_entries = 0;  // 4 x rows + 2 x items
+  double* buf = nullptr;  // r, z0, g0, wmean, wm2 (n_entries each), then the chain scalars
+  uint64_t* iter = nullptr;
+};
+
+namespace {
+
+bool chains_complete(const nr_hmc_chains* ch) {
+  const void* need[] = {ch->z_rows, ch->z_inst, ch->kind_rows, ch->kind_inst, ch->a_rows,
+                        ch->b_rows, ch->a_inst, ch->b_inst, ch->inv_mass_rows,
+                        ch->inv_mass_inst, ch->step, ch->layers, ch->scale, ch->bkg,
+                        ch->logL, ch->g_rows, ch->g_inst, ch->potential, ch->accept_prob,
+                        ch->energy_error, ch->n_accept, ch->n_divergent};
+  for (const void* q : need)
+    if (!q) return false;
+  return true;
+}
+
+nr_status check_chains(const nr_hmc* h, const nr_values* data, const nr_hmc_chains* ch, void* ws,
+                       size_t ws_bytes) {
+  if (!h || !data || !ch) return NR_EINVAL;
+  nr_values v = *data;
+  v.layers = ch->layers;
+  v.scale = ch->scale;
+  v.bkg = ch->bkg;
+  nr_status s = check_call(h->plan, &v, true);
+  if (s != NR_OK) return s;
+  if (h->plan->n_items == 0) return NR_OK;
+  if (!chains_complete(ch)) return NR_EINVAL;
+  const size_t bytes = sizeof(double) * op_doubles(h->plan, NR_OP_LOGLIK_GRAD);
+  if (bytes > 0 && (!ws || ws_bytes < bytes)) return NR_EWORKSPACE;
+  return NR_OK;
+}
+
+HmcArgs hmc_args(const nr_hmc* h, const nr_hmc_chains* ch) {
+  const nr_plan* p = h->plan;
+  HmcArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n_items = p->n_items;
+  a.n_row_entries = p->row_off.back() * 4;
+  a.row_off = p->d_row_off;
+  a.row_kind = p->d_row_kind;
+  a.z_rows = ch->z_rows;
+  a.z_inst = ch->z_inst;
+  a.kind_rows = ch->kind_rows;
+  a.kind_inst = ch->kind_inst;
+  a.a_rows = ch->a_rows;
+  a.b_rows = ch->b_rows;
+  a.a_inst = ch->a_inst;
+  a.b_inst = ch->b_inst;
+  a.im_rows = ch->inv_mass_rows;
+  a.im_inst = ch->inv_mass_inst;
+  a.step = ch->step;
+  a.layers = ch->layers;
+  a.scale = ch->scale;
+  a.bkg = ch->bkg;
+  a.logL = ch->logL;
+  a.g_rows = ch->g_rows;
+  a.g_inst = ch->g_inst;
+  a.U = ch->potential;
+  a.accept_prob = ch->accept_prob;
+  a.energy_error = ch->energy_error;
+  a.n_accept = ch->n_accept;
+  a.n_divergent = ch->n_divergent;
+  const int64_t n = h->n_entries;
+  a.r = h->buf;
+  a.z0 = h->buf + n;
+  a.g0 = h->buf + 2 * n;
+  a.wmean = h->buf + 3 * n;
+  a.wm2 = h->buf + 4 * n;
+  a.cs = h->buf + 5 * n;
+  a.iter = h->iter;
+  a.seed = h->cfg.seed;
+  a.max_energy_error = h->cfg.max_energy_error;
+  a.target_accept = h->cfg.target_accept;
+  return a;
+}
+
+}  // namespace
+
+struct nr_vi_mvn {
+  const nr_plan* plan = nullptr;
+  nr_vi_mvn_config cfg;
+  int32_t P = 0, rows = 0;
+  double* buf = nullptr;  // eps, z, h, f, layers, scale, bkg, logL, g_rows, g_inst, adam m, v
+  uint64_t* iter = nullptr;
+  MvnArgs args;           // driver-owned pointers and configuration
+};
+
+namespace {
+
+nr_status check_mvn(const nr_vi_mvn* m, const nr_values* data, const nr_vi_mvn_params* prm,
+                    void* ws, size_t ws_bytes) {
+  if (!m || !data || !prm) return NR_EINVAL;
+  const void* need[] = {prm->kind, prm->a, prm->b, prm->theta_fixed, prm->mu, prm->omega,
+                        prm->lam, prm->elbo, prm->grad_mu, prm->grad_omega, prm->grad_lam};
+  for (const void* q : need)
+    if (!q) return NR_EINVAL;
+  nr_values v = *data;
+  v.layers = m->args.layers;
+  v.scale = m->args.scale;
+  v.bkg = m->args.bkg;
+  nr_status s = check_call(m->plan, &v, true);
+  if (s != NR_OK) return s;
+  const size_t bytes = sizeof(double) * op_doubles(m->plan, NR_OP_LOGLIK_GRAD);
+  if (bytes > 0 && (!ws || ws_bytes < bytes)) return NR_EWORKSPACE;
+  return NR_OK;
+}
+
+MvnArgs mvn_args(const nr_vi_mvn* m, const nr_vi_mvn_params* prm) {
+  MvnArgs a = m->args;
+  a.kind = prm->kind;
+  a.a = prm->a;
+  a.b = prm->b;
+  a.theta_fixed = prm->theta_fixed;
+  a.mu = prm->mu;
+  a.omega = prm->omega;
+  a.lam = prm->lam;
+  a.grad_mu = prm->grad_mu;
+  a.grad_omega = prm->grad_omega;
+  a.grad_lam = prm->grad_lam;
+  a.elbo = prm->elbo;
+  return a;
+}
+
+// One step: draws, logL + gradient of every draw, the z-gradients, the
+// per-restart ELBO and gradient, Adam (optional), the iteration tick.
+nr_status enqueue_mvn_step(const nr_vi_mvn* m, const nr_values* data,
+                           const nr_vi_mvn_params* prm, bool adam, void* ws, hipStream_t s,
+                           bool events) {
+  const MvnArgs a = mvn_args(m, prm);
+  nr_values v = *data;
+  v.layers = a.layers;
+  v.scale = a.scale;
+  v.bkg = a.bkg;
+  hipError_t e = launch_mvn(kMvnSample, a, s);
+  if (e != hipSuccess) return hip_fail(e, "mvn sample");
+  nr_status r = enqueue_grad(m->plan, &v, a.logL, a.g_rows, a.g_inst, ws, s, events);
+  if (r != NR_OK) return r;
+  e = launch_mvn(kMvnChain, a, s);
+  if (e == hipSuccess) e = launch_mvn(kMvnReduce, a, s);
+  if (e == hipSuccess && adam) e = launch_mvn(kMvnAdam, a, s);
+  if (e == hipSuccess) e = launch_mvn(kMvnTick, a, s);
+  return e == hipSuccess ? NR_OK : hip_fail(e, "mvn launch");
+}
+
+nr_values chain_values(const nr_values* data, const nr_hmc_chains* ch) {
+  nr_values v = *data;
+  v.layers = ch->layers;
+  v.scale = ch->scale;
+  v.bkg = ch->bkg;
+  return v;
+}
+
+// One transition (Sec. 2.3): begin (momentum, first half kick), then per
+// leapfrog step drift, logL + gradient, kick (a full kick where two half
+// kicks meet), then the accept.
+nr_status enqueue_transition(const nr_hmc* h, const nr_values* data, const nr_hmc_chains* ch,
+                             int32_t adapt, void* ws, hipStream_t s, bool events) {
+  const nr_plan* p = h->plan;
+  if (p->n_items == 0) return NR_OK;
+  const HmcArgs a = hmc_args(h, ch);
+  const nr_values v = chain_values(data, ch);
+  hipError_t e = launch_hmc(kHmcBegin, a, 0, 0.0, s);
+  if (e != hipSuccess) return hip_fail(e, "hmc begin");
+  const int L = h->cfg.n_leapfrog;
+  for (int k = 0; k < L; ++k) {
+    e = launch_hmc(kHmcDrift, a, 0, 0.0, s);
+    if (e != hipSuccess) return hip_fail(e, "hmc drift");
+    nr_status r = enqueue_grad(p, &v, ch->logL, ch->g_rows, ch->g_inst, ws, s, events);
+    if (r != NR_OK) return r;
+    e = launch_hmc(kHmcKick, a, 0, (k + 1 < L) ? 1.0 : 0.5, s);
+    if (e != hipSuccess) return hip_fail(e, "hmc kick");
+  }
+  e = launch_hmc(kHmcEnd, a, adapt, 0.0, s);
+  return e == hipSuccess ? NR_OK : hip_fail(e, "hmc end");
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -449,7 +647,9 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
     int32_t item, p0, count;
     int64_t rec0;  // record of its first point
   };
-  std::vector<std::vector<Wu>> fwd_units(kNumBuckets), grad_units(kNumBuckets);
+  // one list per bucket, then the deep list (kDeepBucket)
+  std::vector<std::vector<Wu>> fwd_units(kNumBuckets + 1), grad_units(kNumBuckets + 1);
+  int scan_ch = 0;
   std::map<std::pair<int, int>, std::vector<Tail>> tails;  // (depth, nodes)
   std::vector<int64_t> ll_first(nI), ll_offs, gr_first(nI), gr_offs;
   std::vector<int32_t> ll_count(nI), gr_count(nI);
@@ -460,7 +660,7 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
     const int N = (int)(p->row_off[b + 1] - p->row_off[b]) - 2;
     const int K = p->dqq[s] > 0.0 ? kSmearNodes : 1;
     const int bk = bucket_of(N);
-    const int64_t rsz = 3 + 4 * (N + 2);
+    const int64_t rsz = 4 + 4 * (N + 2);
     p->out_off[b + 1] = p->out_off[b] + nq;
     const int nwu = (int)((nq + kWuPoints - 1) / kWuPoints);
     ll_first[b] = (int64_t)ll_offs.size();
@@ -470,6 +670,19 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
       const double pts = (double)std::min<int64_t>(kWuPoints, nq - p0);
       fwd_units[bk].push_back({b, p0, rec_ll, pts * K * (N + 1)});
       ll_offs.push_back(rec_ll++);
+    }
+    p->max_rows = std::max(p->max_rows, N + 2);
+    if (bk == kDeepBucket) {
+      // one unit per data point; the wave splits the layers
+      gr_first[b] = (int64_t)gr_offs.size();
+      gr_count[b] = (int32_t)nq;
+      scan_ch = std::max(scan_ch, (N + 1 + 63) / 64);
+      for (int64_t k = 0; k < nq; ++k) {
+        grad_units[bk].push_back({b, (int32_t)k, rec_gr, (double)K * (N + 1) * 64});
+        gr_offs.push_back(rec_gr);
+        rec_gr += rsz;
+      }
+      continue;
     }
     const int nfull = (int)(nq / kWuPoints);
     const int ntail = (int)(nq % kWuPoints);
@@ -526,7 +739,7 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
 
   // full-unit launches: one per non-empty bucket, deepest first, LPT order
   auto make_full = [&](std::vector<std::vector<Wu>>& units, std::vector<Launch>& out_list) {
-    for (int bk = kNumBuckets - 1; bk >= 0; --bk) {
+    for (int bk = kNumBuckets; bk >= 0; --bk) {
       auto& v = units[bk];
       if (v.empty() || e != hipSuccess) continue;
       std::stable_sort(v.begin(), v.end(), [](const Wu& x, const Wu& y) { return x.cost > y.cost; });
@@ -540,7 +753,8 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
       }
       Launch L;
       L.bucket = bk;
-      L.store = p->bucket_store[bk];
+      L.store = bk < kNumBuckets && p->bucket_store[bk];
+      L.scan_ch = bk == kDeepBucket ? scan_ch : 0;
       L.n_wu = (int)v.size();
       e = upload(&L.item, it);
       keep(L.item);
@@ -551,6 +765,8 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
   };
   make_full(fwd_units, p->launches_fwd);
   make_full(grad_units, p->launches_grad);
+  if (e == hipSuccess && scan_ch > 0) e = prepare_grad_scan(scan_ch);
+  if (e == hipSuccess) e = prepare_reduce(p->max_rows);
 
   // tail launches: per (depth, nodes) group, largest tails first, first fit
   // into 64-lane units; then one launch per bucket over all its groups
@@ -639,6 +855,226 @@ nr_status nr_leapfrog_graph_create(const nr_plan* p, const nr_values* data, cons
   e = hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     s = enqueue_leapfrog(p, data, st, dt, n_steps, ws, g->stream, false);
+    hipError_t e2 = hipStreamEndCapture(g->stream, &g->graph);
+    if (s == NR_OK && e2 != hipSuccess) s = hip_fail(e2, "end capture");
+  } else {
+    s = hip_fail(e, "begin capture");
+  }
+  if (s == NR_OK) {
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) s = hip_fail(e, "graph instantiate");
+  }
+  if (s != NR_OK) {
+    nr_graph_destroy(g);
+    return s;
+  }
+  *out = g;
+  return NR_OK;
+}
+
+nr_status nr_hmc_create(const nr_plan* p, const nr_hmc_config* cfg, nr_hmc** out) {
+  if (!out) return NR_EINVAL;
+  *out = nullptr;
+  if (!p || !cfg || cfg->n_leapfrog < 1 || !(cfg->max_energy_error > 0.0) ||
+      !(cfg->target_accept > 0.0 && cfg->target_accept < 1.0))
+    return NR_EINVAL;
+  nr_hmc* h = new nr_hmc();
+  h->plan = p;
+  h->cfg = *cfg;
+  h->n_entries = p->row_off.back() * 4 + 2 * (int64_t)p->n_items;
+  const size_t nd = (size_t)(5 * h->n_entries + (int64_t)kChainScalars * p->n_items);
+  hipError_t e = hipSuccess;
+  if (nd > 0) {
+    e = hipMalloc(reinterpret_cast<void**>(&h->buf), nd * sizeof(double));
+    if (e == hipSuccess) e = hipMemset(h->buf, 0, nd * sizeof(double));
+  }
+  if (e == hipSuccess && p->n_items > 0) {
+    e = hipMalloc(reinterpret_cast<void**>(&h->iter), p->n_items * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMemset(h->iter, 0, p->n_items * sizeof(uint64_t));
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    nr_hmc_destroy(h);
+    (void)hip_fail(e, "hmc state");
+    return (e == hipErrorOutOfMemory) ? NR_ENOMEM : NR_EHIP;
+  }
+  *out = h;
+  return NR_OK;
+}
+
+nr_status nr_hmc_destroy(nr_hmc* h) {
+  if (!h) return NR_OK;
+  if (h->buf) (void)hipFree(h->buf);
+  if (h->iter) (void)hipFree(h->iter);
+  delete h;
+  return NR_OK;
+}
+
+nr_status nr_hmc_init(nr_hmc* h, const nr_values* data, const nr_hmc_chains* ch,
+                      int32_t from_theta, void* ws, size_t ws_bytes, void* stream) {
+  nr_status s = check_chains(h, data, ch, ws, ws_bytes);
+  if (s != NR_OK) return s;
+  if (h->plan->n_items == 0) return NR_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const HmcArgs a = hmc_args(h, ch);
+  hipError_t e = launch_hmc(kHmcTheta, a, from_theta ? 1 : 0, 0.0, st);
+  if (e != hipSuccess) return hip_fail(e, "hmc theta");
+  const nr_values v = chain_values(data, ch);
+  s = enqueue_grad(h->plan, &v, ch->logL, ch->g_rows, ch->g_inst, ws, st, true);
+  if (s != NR_OK) return s;
+  e = launch_hmc(kHmcPotential, a, 0, 0.0, st);
+  return e == hipSuccess ? NR_OK : hip_fail(e, "hmc potential");
+}
+
+nr_status nr_hmc_transition(nr_hmc* h, const nr_values* data, const nr_hmc_chains* ch,
+                            int32_t adapt, void* ws, size_t ws_bytes, void* stream) {
+  nr_status s = check_chains(h, data, ch, ws, ws_bytes);
+  if (s != NR_OK) return s;
+  if (adapt & ~(NR_HMC_ADAPT_MASS | NR_HMC_ADAPT_STEP)) return NR_EINVAL;
+  return enqueue_transition(h, data, ch, adapt, ws, (hipStream_t)stream, true);
+}
+
+nr_status nr_hmc_graph_create(nr_hmc* h, const nr_values* data, const nr_hmc_chains* ch,
+                              int32_t adapt, int32_t n_transitions, void* ws, size_t ws_bytes,
+                              nr_graph** out) {
+  if (!out) return NR_EINVAL;
+  *out = nullptr;
+  nr_status s = check_chains(h, data, ch, ws, ws_bytes);
+  if (s != NR_OK) return s;
+  if (n_transitions < 0 || (adapt & ~(NR_HMC_ADAPT_MASS | NR_HMC_ADAPT_STEP))) return NR_EINVAL;
+  nr_graph* g = new nr_graph();
+  hipError_t e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete g;
+    return hip_fail(e, "graph stream");
+  }
+  e = hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (int32_t t = 0; t < n_transitions && s == NR_OK; ++t)
+      s = enqueue_transition(h, data, ch, adapt, ws, g->stream, false);
+    hipError_t e2 = hipStreamEndCapture(g->stream, &g->graph);
+    if (s == NR_OK && e2 != hipSuccess) s = hip_fail(e2, "end capture");
+  } else {
+    s = hip_fail(e, "begin capture");
+  }
+  if (s == NR_OK) {
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) s = hip_fail(e, "graph instantiate");
+  }
+  if (s != NR_OK) {
+    nr_graph_destroy(g);
+    return s;
+  }
+  *out = g;
+  return NR_OK;
+}
+
+nr_status nr_hmc_adapt(nr_hmc* h, const nr_hmc_chains* ch, int32_t actions, void* stream) {
+  if (!h || !ch) return NR_EINVAL;
+  if (actions & ~(NR_HMC_MASS_WINDOW_END | NR_HMC_STEP_RESTART | NR_HMC_STEP_FINAL))
+    return NR_EINVAL;
+  if (h->plan->n_items == 0 || actions == 0) return NR_OK;
+  if (!chains_complete(ch)) return NR_EINVAL;
+  hipError_t e = launch_hmc(kHmcAdapt, hmc_args(h, ch), actions, 0.0, (hipStream_t)stream);
+  return e == hipSuccess ? NR_OK : hip_fail(e, "hmc adapt");
+}
+
+nr_status nr_vi_mvn_create(const nr_plan* p, const nr_vi_mvn_config* cfg, nr_vi_mvn** out) {
+  if (!out) return NR_EINVAL;
+  *out = nullptr;
+  if (!p || !cfg || cfg->n_restarts < 1 || cfg->n_draws < 1 ||
+      (int64_t)cfg->n_restarts * cfg->n_draws != p->n_items || p->uniform_rows < 2 ||
+      p->uniform_rows > kMaxLayers + 2 ||
+      !(cfg->lr > 0.0) || !(cfg->beta1 >= 0.0 && cfg->beta1 < 1.0) ||
+      !(cfg->beta2 >= 0.0 && cfg->beta2 < 1.0) || !(cfg->adam_eps > 0.0))
+    return NR_EINVAL;
+  nr_vi_mvn* m = new nr_vi_mvn();
+  m->plan = p;
+  m->cfg = *cfg;
+  m->rows = p->uniform_rows;
+  m->P = 4 * m->rows + 2;
+  const int64_t items = p->n_items, P = m->P, R = cfg->n_restarts;
+  const int64_t n_adam = R * (2 * P + P * P);
+  const int64_t sizes[] = {items * P, items * P, items * P, items, items * 4 * m->rows,
+                           items, items, items, items * 4 * m->rows, items * 2, n_adam, n_adam};
+  int64_t total = 0;
+  for (int64_t v : sizes) total += v;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&m->buf), (size_t)total * sizeof(double));
+  if (e == hipSuccess) e = hipMemset(m->buf, 0, (size_t)total * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&m->iter), sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMemset(m->iter, 0, sizeof(uint64_t));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    nr_vi_mvn_destroy(m);
+    (void)hip_fail(e, "mvn state");
+    return (e == hipErrorOutOfMemory) ? NR_ENOMEM : NR_EHIP;
+  }
+  double* ptrs[12];
+  double* q = m->buf;
+  for (int k = 0; k < 12; ++k) {
+    ptrs[k] = q;
+    q += sizes[k];
+  }
+  MvnArgs& a = m->args;
+  std::memset(&a, 0, sizeof(a));
+  a.R = cfg->n_restarts;
+  a.S = cfg->n_draws;
+  a.P = m->P;
+  a.rows = m->rows;
+  a.eps = ptrs[0];
+  a.z = ptrs[1];
+  a.h = ptrs[2];
+  a.f = ptrs[3];
+  a.layers = ptrs[4];
+  a.scale = ptrs[5];
+  a.bkg = ptrs[6];
+  a.logL = ptrs[7];
+  a.g_rows = ptrs[8];
+  a.g_inst = ptrs[9];
+  a.adam_m = ptrs[10];
+  a.adam_v = ptrs[11];
+  a.iter = m->iter;
+  a.seed = cfg->seed;
+  a.lr = cfg->lr;
+  a.beta1 = cfg->beta1;
+  a.beta2 = cfg->beta2;
+  a.adam_eps = cfg->adam_eps;
+  *out = m;
+  return NR_OK;
+}
+
+nr_status nr_vi_mvn_destroy(nr_vi_mvn* m) {
+  if (!m) return NR_OK;
+  if (m->buf) (void)hipFree(m->buf);
+  if (m->iter) (void)hipFree(m->iter);
+  delete m;
+  return NR_OK;
+}
+
+nr_status nr_vi_mvn_step(nr_vi_mvn* m, const nr_values* data, const nr_vi_mvn_params* prm,
+                         int32_t adam, void* ws, size_t ws_bytes, void* stream) {
+  nr_status s = check_mvn(m, data, prm, ws, ws_bytes);
+  if (s != NR_OK) return s;
+  return enqueue_mvn_step(m, data, prm, adam != 0, ws, (hipStream_t)stream, true);
+}
+
+nr_status nr_vi_mvn_graph_create(nr_vi_mvn* m, const nr_values* data, const nr_vi_mvn_params* prm,
+                                 int32_t n_steps, void* ws, size_t ws_bytes, nr_graph** out) {
+  if (!out) return NR_EINVAL;
+  *out = nullptr;
+  nr_status s = check_mvn(m, data, prm, ws, ws_bytes);
+  if (s != NR_OK) return s;
+  if (n_steps < 0) return NR_EINVAL;
+  nr_graph* g = new nr_graph();
+  hipError_t e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete g;
+    return hip_fail(e, "graph stream");
+  }
+  e = hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (int32_t t = 0; t < n_steps && s == NR_OK; ++t)
+      s = enqueue_mvn_step(m, data, prm, true, ws, g->stream, false);
     hipError_t e2 = hipStreamEndCapture(g->stream, &g->graph);
     if (s == NR_OK && e2 != hipSuccess) s = hip_fail(e2, "end capture");
   } else {
@@ -789,6 +1225,18 @@ nr_status nr_reflectivity_vjp(const nr_plan* p, const nr_values* v, const double
   const size_t need = sizeof(double) * op_doubles(p, NR_OP_LOGLIK_GRAD);
   if (need > 0 && (!ws || ws_bytes < need)) return NR_EWORKSPACE;
   return enqueue_grad(p, v, dot, g_rows, g_inst, ws, (hipStream_t)stream, true, seed);
+}
+
+nr_status nr_loglik_grad_res(const nr_plan* p, const nr_values* v, double* logL, double* g_rows,
+                             double* g_inst, double* g_res, void* ws, size_t ws_bytes,
+                             void* stream) {
+  nr_status st = check_call(p, v, true);
+  if (st != NR_OK) return st;
+  if (p->n_items == 0) return NR_OK;
+  if (!logL || !g_rows || !g_inst || !g_res) return NR_EINVAL;
+  const size_t need = sizeof(double) * op_doubles(p, NR_OP_LOGLIK_GRAD);
+  if (need > 0 && (!ws || ws_bytes < need)) return NR_EWORKSPACE;
+  return enqueue_grad(p, v, logL, g_rows, g_inst, ws, (hipStream_t)stream, true, nullptr, g_res);
 }
 
 nr_status nr_loglik_grad(const nr_plan* p, const nr_values* v, double* logL, double* g_rows,

@@ -257,12 +257,21 @@ __device__ __forceinline__ RootT<float> kz_root(float x, float y) {
   return out;
 }
 
-// Smearing node q = Q + ((dQ/Q) Q / (2 sqrt(2 ln 2))) t, in this order, no FMA.
-__device__ __forceinline__ double smear_node(double Q, double dqq, double t) {
+// Width of the smearing Gaussian of one point: sigma_Q = (dQ/Q) Q /
+// (2 sqrt(2 ln 2)), or dQ / (2 sqrt(2 ln 2)) for a given per-point FWHM; and
+// the node q = Q + sigma_Q t.  In this order, no FMA.
+__device__ __forceinline__ double smear_sigma_rel(double Q, double dqq) {
 #pragma clang fp contract(off)
   double s = dqq * Q;
-  s = s / kFwhmPerSigma;
-  return Q + s * t;
+  return s / kFwhmPerSigma;
+}
+__device__ __forceinline__ double smear_sigma_abs(double dq) {
+#pragma clang fp contract(off)
+  return dq / kFwhmPerSigma;
+}
+__device__ __forceinline__ double smear_at(double Q, double sig, double t) {
+#pragma clang fp contract(off)
+  return Q + sig * t;
 }
 
 // Wave-wide sum of a double (all 64 lanes end with the total), fixed order.

@@ -43,10 +43,15 @@ constexpr int kBucketLmax[] = {1, 2, 4, 6, 8, 10, 12, 14, 16, 18, 20, 24, 28, 32
 constexpr int kNumBuckets = sizeof(kBucketLmax) / sizeof(int);
 static_assert(kNumBuckets == NR_NUM_BUCKETS, "bucket table and ABI disagree");
 
+// Items deeper than the unrolled buckets form one more work list, served by
+// the parallel-in-layers scan kernel (nr_kernels_scan.hip).
+constexpr int kDeepBucket = kNumBuckets;
+constexpr int kMaxDeepLayers = NR_MAX_DEEP_LAYERS;
+constexpr int kScanMaxChunk = (kMaxDeepLayers + 1 + 63) / 64;  // levels per lane
 inline int bucket_of(int N) {
   for (int b = 0; b < kNumBuckets; ++b)
     if (N <= kBucketLmax[b]) return b;
-  return -1;
+  return kDeepBucket;
 }
 
 struct KernelArgs {
@@ -64,6 +69,9 @@ struct KernelArgs {
   const int64_t* row_off;
   const double* dq_over_q;
   const int64_t* out_off;
+  // resolution (caller-owned, optional): per-point FWHM, per-item dQ/Q
+  const double* dq;
+  const double* dqq_item;
   // values (caller-owned)
   const double* q;
   const double* r_obs;
@@ -98,6 +106,8 @@ struct ReduceArgs {
   double* logL;
   double* g_rows;
   double* g_inst;
+  double* g_res;  // optional: dlogL/d(dQ/Q) per item
+  int32_t max_rows;  // the largest rows of any item (record length)
 };
 
 hipError_t launch_item_consts(const int64_t* row_off, const double* layers, double* rec,
@@ -105,10 +115,14 @@ hipError_t launch_item_consts(const int64_t* row_off, const double* layers, doub
 // precision: NR_F64 or NR_F32
 hipError_t launch_forward(int precision, int op, const KernelArgs& a, int n_wu, hipStream_t st);
 // store: the store variant (only for buckets within store_max_layers)
-hipError_t launch_grad(int precision, int bucket, bool store, bool tail, const KernelArgs& a,
+// Forms of the gradient kernel: the recompute form, the store form (buckets up
+// to the precision's store limit), and the recompute form that also
+// accumulates the derivative with respect to the relative resolution.
+enum GradForm { kFormRecompute = 0, kFormStore = 1, kFormRecomputeRes = 2 };
+hipError_t launch_grad(int precision, int bucket, int form, bool tail, const KernelArgs& a,
                        int n_wu, hipStream_t st);
 hipError_t launch_forward_f32(int op, const KernelArgs& a, int n_wu, hipStream_t st);
-hipError_t launch_grad_f32(int bucket, bool store, bool tail, const KernelArgs& a, int n_wu,
+hipError_t launch_grad_f32(int bucket, int form, bool tail, const KernelArgs& a, int n_wu,
                            hipStream_t st);
 // Deep buckets (index >= kFirstDeepBucket): one object per (precision,
 // bucket), built from nr_kernels_bucket.hip, each exporting
@@ -119,9 +133,9 @@ hipError_t launch_grad_f32(int bucket, bool store, bool tail, const KernelArgs& 
 struct F64;
 struct F32;
 #define NR_DECLARE_DEEP(LM)                                                                  \
-  hipError_t NR_DEEP_LAUNCHER(F64, LM)(bool store, bool tail, const KernelArgs& a, int n_wu, \
+  hipError_t NR_DEEP_LAUNCHER(F64, LM)(int form, bool tail, const KernelArgs& a, int n_wu,  \
                                        hipStream_t st);                                      \
-  hipError_t NR_DEEP_LAUNCHER(F32, LM)(bool store, bool tail, const KernelArgs& a, int n_wu, \
+  hipError_t NR_DEEP_LAUNCHER(F32, LM)(int form, bool tail, const KernelArgs& a, int n_wu,  \
                                        hipStream_t st);
 NR_BUCKETS_DEEP(NR_DECLARE_DEEP)
 #undef NR_DECLARE_DEEP
@@ -135,6 +149,14 @@ inline int store_max_layers(int precision) {
 // (10 layers: 0.56 vs 0.60); FP32 store wins up to 8 layers.
 inline int default_store_layers(int precision) { return precision == NR_F32 ? 8 : 4; }
 hipError_t launch_reduce(int op, const ReduceArgs& a, hipStream_t st);
+// Allows the gradient reduction its dynamic LDS for records of max_rows media.
+hipError_t prepare_reduce(int max_rows);
+// The scan kernel for items deeper than kMaxLayers: one wave per (item,
+// point) unit, ch_max = the largest levels-per-lane of the launch's items.
+hipError_t launch_grad_scan(bool res, int ch_max, const KernelArgs& a, int n_wu, hipStream_t st);
+size_t scan_lds_bytes(int ch_max);
+// Allows the scan kernels their dynamic LDS (over 64 KB for deep chunks).
+hipError_t prepare_grad_scan(int ch_max);
 
 hipError_t launch_kick(int64_t n_row_entries, int64_t n_inst, double* mom_rows,
                        const double* g_rows, double* mom_inst, const double* g_inst, double h,
@@ -152,5 +174,92 @@ hipError_t launch_vi_reduce(int64_t n_samples, int P, int rows, const double* om
                             double* grad_omega, double* elbo, hipStream_t st);
 hipError_t launch_tie_sum(int64_t n_out, const int64_t* first, const int64_t* src,
                           const double* in, double* out, hipStream_t st);
+
+// Arguments of the per-chain HMC kernels: the caller's chain arrays
+// (nr_hmc_chains), the plan's structure, and the driver's own device state.
+struct HmcArgs {
+  int32_t n_items;
+  int64_t n_row_entries;  // 4 x rows; instrument entries follow in the driver's arrays
+  const int64_t* row_off;
+  const uint8_t* row_kind;
+  // caller's chains
+  double* z_rows;
+  double* z_inst;
+  const uint8_t* kind_rows;
+  const uint8_t* kind_inst;
+  const double* a_rows;
+  const double* b_rows;
+  const double* a_inst;
+  const double* b_inst;
+  double* im_rows;
+  double* im_inst;
+  double* step;
+  double* layers;
+  double* scale;
+  double* bkg;
+  double* logL;
+  double* g_rows;
+  double* g_inst;
+  double* U;
+  double* accept_prob;
+  double* energy_error;
+  int32_t* n_accept;
+  int32_t* n_divergent;
+  // driver state: momentum, saved position and gradient, Welford sums (one
+  // per entry each), per-chain scalars, iteration counters
+  double* r;
+  double* z0;
+  double* g0;
+  double* wmean;
+  double* wm2;
+  double* cs;
+  uint64_t* iter;
+  // configuration
+  uint64_t seed;
+  double max_energy_error;
+  double target_accept;
+};
+constexpr int kChainScalars = 8;
+enum HmcKernel { kHmcTheta, kHmcPotential, kHmcBegin, kHmcDrift, kHmcKick, kHmcEnd, kHmcAdapt };
+// arg: from_theta (kHmcTheta), adaptation bits (kHmcEnd), actions (kHmcAdapt);
+// frac: the kick's fraction of the step (kHmcKick)
+hipError_t launch_hmc(int which, const HmcArgs& h, int arg, double frac, hipStream_t st);
+
+// Arguments of the full-rank Gaussian VI kernels: the caller's variational
+// parameters (nr_vi_mvn_params) and the driver's per-draw arrays.
+constexpr int kMvnMaxEntries = 4 * (kMaxLayers + 2) + 2;
+struct MvnArgs {
+  int32_t R, S, P, rows;
+  const uint8_t* kind;
+  const double* a;
+  const double* b;
+  const double* theta_fixed;
+  double* mu;
+  double* omega;
+  double* lam;
+  double* grad_mu;
+  double* grad_omega;
+  double* grad_lam;
+  double* elbo;
+  // driver state: per draw eps, z, h (P each), f; the draws' parameters,
+  // logL and gradient; Adam moments; the iteration counter
+  double* eps;
+  double* z;
+  double* h;
+  double* f;
+  double* layers;
+  double* scale;
+  double* bkg;
+  double* logL;
+  double* g_rows;
+  double* g_inst;
+  double* adam_m;
+  double* adam_v;
+  uint64_t* iter;
+  uint64_t seed;
+  double lr, beta1, beta2, adam_eps;
+};
+enum MvnKernel { kMvnSample, kMvnChain, kMvnReduce, kMvnAdam, kMvnTick };
+hipError_t launch_mvn(int which, const MvnArgs& v, hipStream_t st);
 
 }  // namespace nr

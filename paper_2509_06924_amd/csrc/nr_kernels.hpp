@@ -255,7 +255,17 @@ struct WuInfo {
   int64_t qoff, roff;
   bool active;
   double Q, dqq;
+  double sig;      // sigma_Q of the point
+  bool smeared;    // the dataset is smeared (17 nodes)
+  bool pointwise;  // widths given per point (no width derivative)
 };
+
+__device__ __forceinline__ void resolution_setup(const KernelArgs& a, WuInfo& u, int64_t ip) {
+  u.smeared = a.dq_over_q[u.ds] > 0.0;
+  u.dqq = a.dqq_item ? a.dqq_item[u.item] : a.dq_over_q[u.ds];
+  u.pointwise = a.dq != nullptr;
+  u.sig = u.pointwise ? smear_sigma_abs(a.dq[ip]) : smear_sigma_rel(u.Q, u.dqq);
+}
 
 __device__ __forceinline__ WuInfo wu_setup(const KernelArgs& a, int w, int lane) {
   WuInfo u;
@@ -270,7 +280,7 @@ __device__ __forceinline__ WuInfo wu_setup(const KernelArgs& a, int w, int lane)
   u.active = u.i < u.nq;
   // idle lanes evaluate the WU's first point and discard the result
   u.Q = a.q[u.qoff + (u.active ? u.i : p0)];
-  u.dqq = a.dq_over_q[u.ds];
+  resolution_setup(a, u, u.qoff + (u.active ? u.i : p0));
   return u;
 }
 
@@ -292,7 +302,7 @@ __device__ __forceinline__ WuInfo tail_setup(const KernelArgs& a, int w, int lan
   u.nq = (int)(a.q_off[u.ds + 1] - u.qoff);
   u.roff = a.row_off[u.item];
   u.Q = a.q[u.qoff + u.i];
-  u.dqq = a.dq_over_q[u.ds];
+  resolution_setup(a, u, u.qoff + u.i);
   return u;
 }
 
@@ -321,11 +331,11 @@ __global__ __launch_bounds__(64) void k_reflectivity(KernelArgs a) {
   const int w = blockIdx.x;
   const WuInfo u = wu_setup(a, w, lane);
   stage_shared(s, lane, a.rule);
-  const int K = (u.dqq > 0.0) ? kSmearNodes : 1;
+  const int K = u.smeared ? kSmearNodes : 1;
   double Rsm = 0.0;
   bool badq = !(u.Q > 0.0);
   for (int k = 0; k < K; ++k) {
-    const double q = (K == 1) ? u.Q : smear_node(u.Q, u.dqq, ld(s.t[k]));
+    const double q = (K == 1) ? u.Q : smear_at(u.Q, u.sig, ld(s.t[k]));
     badq |= !(q > 0.0);
     const double wk = (K == 1) ? 1.0 : ld(s.w[k]);
     Rsm += wk * node_reflectivity(s.tab, item_layers<P>(a, u.roff, u.N, k), u.N, q);
@@ -365,11 +375,11 @@ __global__ __launch_bounds__(64) void k_loglik(KernelArgs a) {
   const int w = blockIdx.x;
   const WuInfo u = wu_setup(a, w, lane);
   stage_shared(s, lane, a.rule);
-  const int K = (u.dqq > 0.0) ? kSmearNodes : 1;
+  const int K = u.smeared ? kSmearNodes : 1;
   double Rsm = 0.0;
   bool badq = !(u.Q > 0.0);
   for (int k = 0; k < K; ++k) {
-    const double q = (K == 1) ? u.Q : smear_node(u.Q, u.dqq, ld(s.t[k]));
+    const double q = (K == 1) ? u.Q : smear_at(u.Q, u.sig, ld(s.t[k]));
     badq |= !(q > 0.0);
     const double wk = (K == 1) ? 1.0 : ld(s.w[k]);
     Rsm += wk * node_reflectivity(s.tab, item_layers<P>(a, u.roff, u.N, k), u.N, q);
@@ -470,15 +480,27 @@ __device__ __forceinline__ void acc_dd(double& acc, cd kz, cd w) {
 __device__ __forceinline__ void acc_dd(double& acc, cf kz, cf w) {
   acc += 2.0 * (double)(kz.im * w.re - kz.re * w.im);
 }
-// acc += wbar = conj(dkz/dw) kzbar = conj(1/(2 kz)) kzbar = kz kzbar / (2 |kz|^2)
-__device__ __forceinline__ void acc_wbar(cd& acc, cd kz, double inv_abs2, cd kzb) {
+// acc += wbar = conj(dkz/dw) kzbar = conj(1/(2 kz)) kzbar = kz kzbar / (2 |kz|^2),
+// and with RES also sw += Re(wbar) (the node's sum over media, for dR/dq:
+// every w_j moves with kz0^2, dw_j/dq = kz0).
+template <bool RES>
+__device__ __forceinline__ void acc_wbar(cd& acc, double& sw, cd kz, double inv_abs2, cd kzb) {
   const cd p = kz * kzb;
   const double h = 0.5 * inv_abs2;
   acc.re = fma(h, p.re, acc.re);
   acc.im = fma(h, p.im, acc.im);
+  if constexpr (RES) sw = fma(h, p.re, sw);
 }
-__device__ __forceinline__ void acc_wbar(cd& acc, cf kz, float inv_abs2, cf kzb) {
-  acc += widen((0.5f * inv_abs2) * (kz * kzb));
+template <bool RES>
+__device__ __forceinline__ void acc_wbar(cd& acc, double& sw, cf kz, float inv_abs2, cf kzb) {
+  const cd v = widen((0.5f * inv_abs2) * (kz * kzb));
+  acc += v;
+  if constexpr (RES) sw += v.re;
+}
+template <class Cx, class Re>
+__device__ __forceinline__ void acc_wbar(cd& acc, Cx kz, Re inv_abs2, Cx kzb) {
+  double unused = 0.0;
+  acc_wbar<false>(acc, unused, kz, inv_abs2, kzb);
 }
 
 // Per-lane gradient accumulators for one point, FP64 in both precisions:
@@ -615,11 +637,12 @@ struct EfCache {
 // recomputes each medium's wavevector and interface reciprocal, and, below
 // the KS cached levels, the phase and Nevot-Croce factor too.
 // ---------------------------------------------------------------------------
-template <class P, int LMAX, int KS, bool CK>
+template <class P, int LMAX, int KS, bool CK, bool RES>
 __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const Layers<P>& L,
                                                       EfCache<typename P::real, KS>& ef,
                                                       Accum<LMAX>& acc, int lane, double q,
-                                                      double wk, bool& edge) {
+                                                      double wk, bool& edge, double& Hq,
+                                                      double c) {
   using Re = typename P::real;
   using Cx = cx<Re>;
   static_assert(!CK || LMAX % 2 == 0, "checkpointed tape needs an even depth");
@@ -659,6 +682,7 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
   Cx Pb = cmulc(-(r * iP), rbar);
   Cx Qb = cmulc(iP, rbar);
   Cx kzbc = mk(Re(0), Re(0));
+  double sw = 0.0;
 
   // the coefficients of level jj (kz_jj = kzc known), recomputed or from the
   // LDS cache
@@ -693,12 +717,14 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
     const AdjStep<Re> st =
         adjoint_step(Ps, Qs, Pb, Qb, kzc, lv.rn.kz, lv.it, lv.C, ph, lv.e, lv.D);
     kzbc += st.kzb_c;
+    if constexpr (RES)
+      if (jj == 0) Hq = fma(0.5 * c, (double)kzbc.re, Hq);
     acc_re_dot(acc.Hs[jj + 1], st.ub, lv.it.kk);
     if (ph) {
       acc_dd(acc.Hd[jj], kzc, st.w);
-      acc_wbar(acc.Hw[jj], kzc, iac, kzbc);
+      acc_wbar<RES>(acc.Hw[jj], sw, kzc, iac, kzbc);
     }
-    if (jj == LMAX) acc_wbar(acc.Hw[jj + 1], lv.rn.kz, lv.rn.inv_abs2, st.kzb_n);
+    if (jj == LMAX) acc_wbar<RES>(acc.Hw[jj + 1], sw, lv.rn.kz, lv.rn.inv_abs2, st.kzb_n);
     Pb = st.Pb;
     Qb = st.Qb;
     kzbc = st.kzb_n;
@@ -737,6 +763,8 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
       __builtin_amdgcn_sched_barrier(0x0100);  // only LDS reads may move across
     }
   }
+  // Hq += c dR/dq (seeded): dkz0/dq = 1/2 (added at level 0), dw_j/dq = kz0
+  if constexpr (RES) Hq = fma(0.5 * q * c, sw, Hq);
   return (double)cabs2(r);
 }
 
@@ -748,9 +776,11 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
 //   [3 + NR + m]   sum Im wbar_m
 //   [3 + 2NR + m]  sum dl/dd_m
 //   [3 + 3NR + m]  sum Re(conj(ubar) kz_{m-1} kz_m)   (sigma_m factor applied later)
+//   [3 + 4NR]      d/d(dQ/Q) (relative resolution)
 // ---------------------------------------------------------------------------
-template <class P, int LMAX, bool STORE, bool TAIL>
+template <class P, int LMAX, bool STORE, bool TAIL, bool RES>
 __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(KernelArgs a) {
+  static_assert(!(STORE && RES), "the resolution derivative has the recompute form only");
   using Re = typename P::real;
   __shared__ Shared s;
   using Tape = typename std::conditional<STORE, GradTape<Re, LMAX>, char>::type;
@@ -763,7 +793,7 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(K
   const WuInfo u = TAIL ? tail_setup(a, w, lane) : wu_setup(a, w, lane);
   stage_shared(s, lane, a.rule);
   const int N = u.N;
-  const int K = (u.dqq > 0.0) ? kSmearNodes : 1;
+  const int K = u.smeared ? kSmearNodes : 1;
 
   Accum<LMAX> acc;
 #pragma unroll
@@ -774,10 +804,14 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(K
   }
 
   double Rsm = 0.0;
+  double Hq = 0.0;  // sum_k w_k dR(q_k)/dq_k dq_k/d(dQ/Q)
   bool badq = !(u.Q > 0.0);
   bool edge = false;
+  // dq_k/d(dQ/Q) = Q t_k / (2 sqrt(2 ln 2)) for a relative width
+  const double dq_dres = (u.smeared && !u.pointwise) ? u.Q / kFwhmPerSigma : 0.0;
   for (int k = 0; k < K; ++k) {
-    const double q = (K == 1) ? u.Q : smear_node(u.Q, u.dqq, ld(s.t[k]));
+    const double tk = ld(s.t[k]);
+    const double q = (K == 1) ? u.Q : smear_at(u.Q, u.sig, tk);
     badq |= !(q > 0.0);
     const double wk = (K == 1) ? 1.0 : ld(s.w[k]);
     const Layers<P> L = item_layers<P>(a, u.roff, N, k);
@@ -785,8 +819,8 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(K
     if constexpr (STORE)
       R = node_grad_store<P, LMAX>(s.tab, L, tape, acc, lane, q, wk, edge);
     else
-      R = node_grad_recompute<P, LMAX, KS, P::checkpoint(LMAX)>(s.tab, L, efc, acc, lane, q, wk,
-                                                                edge);
+      R = node_grad_recompute<P, LMAX, KS, P::checkpoint(LMAX), RES>(
+          s.tab, L, efc, acc, lane, q, wk, edge, Hq, RES ? dq_dres * tk : 0.0);
     Rsm += wk * R;
   }
   // the item was evaluated at depth LMAX: the copies of the backing below it
@@ -827,7 +861,8 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(K
   flag(a.item_status, u.item, bits);
 
   const int NR = N + 2;
-  const int nf = 3 + 4 * NR;
+  // record of 4 + 4 NR doubles; the last field only in the RES form
+  const int nf = (RES ? 4 : 3) + 4 * NR;
   if constexpr (TAIL) {
     // Lanes of one item are contiguous; idle lanes (key -1) follow the last
     // item.  A segmented inclusive scan over the lanes leaves each item's
@@ -865,10 +900,11 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(K
         seg_put(3 + 3 * NR + m, fac * acc.Hs[m]);
       }
     }
+    if constexpr (RES) seg_put(3 + 4 * NR, fac * Hq);
     return;
   }
   // ---- wave reduction; the sums go through LDS into one coalesced store ----
-  __shared__ double stage[3 + 4 * (LMAX + 2)];
+  __shared__ double stage[4 + 4 * (LMAX + 2)];
   ll = wave_sum(ll);
   gsc = wave_sum(gsc);
   gbk = wave_sum(gbk);
@@ -892,6 +928,10 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(K
       }
     }
   }
+  if constexpr (RES) {
+    const double hq = wave_sum(fac * Hq);
+    if (lane == 0) stage[3 + 4 * NR] = hq;
+  }
   __syncthreads();
   double* rec = a.rec + a.wu_rec[w];
   for (int f = lane; f < nf; f += 64) rec[f] = stage[f];
@@ -913,27 +953,31 @@ hipError_t launch_forward_p(int op, const KernelArgs& a, int n_wu, hipStream_t s
 
 // Launch of one gradient bucket; BUCKETS is the list macro of the buckets
 // this translation unit compiles.
-#define NR_LAUNCH(LM, S)                                                                      \
+#define NR_LAUNCH(LM, S, RES)                                                                 \
   if (tail)                                                                                   \
-    hipLaunchKernelGGL((k_loglik_grad<P, LM, S, true>), dim3(n_wu), dim3(64), 0, st, a);       \
+    hipLaunchKernelGGL((k_loglik_grad<P, LM, S, true, RES>), dim3(n_wu), dim3(64), 0, st, a);  \
   else                                                                                        \
-    hipLaunchKernelGGL((k_loglik_grad<P, LM, S, false>), dim3(n_wu), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_loglik_grad<P, LM, S, false, RES>), dim3(n_wu), dim3(64), 0, st, a);
+// the kernel form (GradForm) of bucket LM
+#define NR_FORMS(LM)                                                                          \
+  if (form == kFormRecomputeRes) {                                                            \
+    NR_LAUNCH(LM, false, true)                                                                \
+  } else if (form == kFormStore) {                                                            \
+    if constexpr (LM <= P::kStoreMax) {                                                       \
+      NR_LAUNCH(LM, true, false)                                                              \
+    } else {                                                                                  \
+      return hipErrorInvalidValue;                                                            \
+    }                                                                                         \
+  } else {                                                                                    \
+    NR_LAUNCH(LM, false, false)                                                               \
+  }
 #define NR_CASE(LM)                                                                           \
   case LM:                                                                                    \
-    if constexpr (LM <= P::kStoreMax) {                                                       \
-      if (store) {                                                                            \
-        NR_LAUNCH(LM, true)                                                                   \
-      } else {                                                                                \
-        NR_LAUNCH(LM, false)                                                                  \
-      }                                                                                       \
-    } else {                                                                                  \
-      if (store) return hipErrorInvalidValue;                                                 \
-      NR_LAUNCH(LM, false)                                                                    \
-    }                                                                                         \
+    NR_FORMS(LM)                                                                              \
     return hipGetLastError();
 #define NR_DEFINE_GRAD_LAUNCHER(NAME, BUCKETS)                                                \
   template <class P>                                                                          \
-  hipError_t NAME(int bucket, bool store, bool tail, const KernelArgs& a, int n_wu,          \
+  hipError_t NAME(int bucket, int form, bool tail, const KernelArgs& a, int n_wu,            \
                   hipStream_t st) {                                                           \
     if (n_wu <= 0) return hipSuccess;                                                         \
     switch (kBucketLmax[bucket]) {                                                            \

@@ -10,21 +10,12 @@
 
 namespace nr {
 
-hipError_t NR_DEEP_LAUNCHER(NR_PREC, NR_BUCKET_LMAX)(bool store, bool tail, const KernelArgs& a,
+hipError_t NR_DEEP_LAUNCHER(NR_PREC, NR_BUCKET_LMAX)(int form, bool tail, const KernelArgs& a,
                                                      int n_wu, hipStream_t st) {
   using P = NR_PREC;
   constexpr int LM = NR_BUCKET_LMAX;
   if (n_wu <= 0) return hipSuccess;
-  if constexpr (LM <= P::kStoreMax) {
-    if (store) {
-      NR_LAUNCH(LM, true)
-    } else {
-      NR_LAUNCH(LM, false)
-    }
-  } else {
-    if (store) return hipErrorInvalidValue;
-    NR_LAUNCH(LM, false)
-  }
+  NR_FORMS(LM)
   return hipGetLastError();
 }
 

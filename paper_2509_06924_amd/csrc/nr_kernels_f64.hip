@@ -7,17 +7,16 @@ namespace nr {
 
 NR_DEFINE_GRAD_LAUNCHER(launch_grad_shallow, NR_BUCKETS_SHALLOW)
 
-// One block of 64 per item, one lane per medium: the item's layer records
+// One block of 64 per item, lanes over the media: the item's layer records
 // (doubles and their float copies for the FP32 variant).
 __global__ __launch_bounds__(64) void k_item_consts(const int64_t* row_off, const double* layers,
                                                     double* rec, float* recf, int n_items) {
   const int b = blockIdx.x;
-  const int m = threadIdx.x;
   if (b >= n_items) return;
   const int64_t r0 = row_off[b];
   const int NR = (int)(row_off[b + 1] - r0);
-  if (m >= NR) return;
   const double* rows = layers + 4 * r0;
+  for (int m = threadIdx.x; m < NR; m += 64) {
   const double rho0 = rows[1];
   auto Af = [&](int j) { return (j == 0) ? 0.0 : kFourPi * (rows[4 * j + 1] - rho0); };
   auto Bf = [&](int j) { return (j == 0) ? 0.0 : kFourPi * fabs(rows[4 * j + 2]); };
@@ -42,6 +41,7 @@ __global__ __launch_bounds__(64) void k_item_consts(const int64_t* row_off, cons
   float* outf = recf + (r0 + m) * kRecFloats;
   for (int f = 0; f < 5; ++f) outf[f] = (float)v[f + 1];
   for (int f = 5; f < kRecFloats; ++f) outf[f] = 0.0f;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -67,7 +67,9 @@ __global__ __launch_bounds__(64) void k_reduce_grad(ReduceArgs a) {
   const int cnt = a.item_wu_count[b];
   const int64_t roff = a.row_off[b];
   const int NR = (int)(a.row_off[b + 1] - roff);
-  const int nf = 3 + 4 * NR;
+  // records hold 4 + 4 NR doubles; the last is written by the resolution
+  // form only
+  const int nf = (a.g_res ? 4 : 3) + 4 * NR;
   for (int f = lane; f < nf; f += 64) {
     double v = 0.0;
     for (int k = 0; k < cnt; ++k) v += a.rec[a.rec_of_wu[first + k] + f];
@@ -101,6 +103,7 @@ __global__ __launch_bounds__(64) void k_reduce_grad(ReduceArgs a) {
     a.logL[b] = fsum[0];
     a.g_inst[2 * b + 0] = fsum[1];
     a.g_inst[2 * b + 1] = fsum[2];
+    if (a.g_res) a.g_res[b] = fsum[3 + 4 * NR];
   }
 }
 
@@ -120,22 +123,29 @@ hipError_t launch_forward(int precision, int op, const KernelArgs& a, int n_wu, 
                              : launch_forward_p<F64>(op, a, n_wu, st);
 }
 
-hipError_t launch_grad(int precision, int bucket, bool store, bool tail, const KernelArgs& a,
+hipError_t launch_grad(int precision, int bucket, int form, bool tail, const KernelArgs& a,
                        int n_wu, hipStream_t st) {
+  if (bucket == kDeepBucket) return hipErrorInvalidValue;  // launch_grad_scan
   if (bucket >= kFirstDeepBucket) {
     switch (kBucketLmax[bucket]) {
 #define NR_DEEP_CASE(LM)                                                             \
   case LM:                                                                           \
-    return precision == NR_F32 ? NR_DEEP_LAUNCHER(F32, LM)(store, tail, a, n_wu, st) \
-                               : NR_DEEP_LAUNCHER(F64, LM)(store, tail, a, n_wu, st);
+    return precision == NR_F32 ? NR_DEEP_LAUNCHER(F32, LM)(form, tail, a, n_wu, st) \
+                               : NR_DEEP_LAUNCHER(F64, LM)(form, tail, a, n_wu, st);
       NR_BUCKETS_DEEP(NR_DEEP_CASE)
 #undef NR_DEEP_CASE
       default:
         return hipErrorInvalidValue;
     }
   }
-  return precision == NR_F32 ? launch_grad_f32(bucket, store, tail, a, n_wu, st)
-                             : launch_grad_shallow<F64>(bucket, store, tail, a, n_wu, st);
+  return precision == NR_F32 ? launch_grad_f32(bucket, form, tail, a, n_wu, st)
+                             : launch_grad_shallow<F64>(bucket, form, tail, a, n_wu, st);
+}
+
+hipError_t prepare_reduce(int max_rows) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_reduce_grad),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(sizeof(double) * (4 + 4 * (size_t)max_rows)));
 }
 
 hipError_t launch_reduce(int op, const ReduceArgs& a, hipStream_t st) {
@@ -143,7 +153,7 @@ hipError_t launch_reduce(int op, const ReduceArgs& a, hipStream_t st) {
   if (op == kOpLoglik) {
     hipLaunchKernelGGL(k_reduce_loglik, dim3((a.n_items + 255) / 256), dim3(256), 0, st, a);
   } else {
-    const size_t shmem = sizeof(double) * (3 + 4 * (kMaxLayers + 2));
+    const size_t shmem = sizeof(double) * (4 + 4 * (size_t)a.max_rows);
     hipLaunchKernelGGL(k_reduce_grad, dim3(a.n_items), dim3(64), shmem, st, a);
   }
   return hipGetLastError();

@@ -216,6 +216,31 @@ def c5_vi(n_samples=8192, nq=1000, L=20, dq_over_q=0.05, rel_width=0.01, seed_of
                  items, {"config": 5, "mu": mu, "eps": eps, "rel_width": rel_width})
 
 
+def microsliced(n_items=64, L=1000, nq=200, dz=2.0, dq_over_q=0.05, seed_offset=6):
+    """Microsliced SLD profiles (hundreds to thousands of slabs): each item
+    samples a smooth two-film profile on silicon in L slices of dz A (small
+    absorption, 0.5 A slice roughness); one dataset of nq log-spaced points."""
+    rng = np.random.default_rng(SEED_BASE + seed_offset)
+    Q = log_grid(0.005, 0.3, nq)
+    Robs, err = synthetic_curve(Q, rng)
+    z = (np.arange(L) + 0.5) * dz
+    span = L * dz
+    items = []
+    for _ in range(n_items):
+        c1, c2 = rng.uniform(0.2, 0.4) * span, rng.uniform(0.6, 0.8) * span
+        w = rng.uniform(0.03, 0.08) * span
+        rows = np.zeros((L + 2, 4))
+        rows[1:L + 1, 0] = dz
+        rows[1:L + 1, 1] = (1.0e-6 + 3.0e-6 / (1 + np.exp(-(z - c1) / w))
+                            - 2.0e-6 / (1 + np.exp(-(z - c2) / w)))
+        rows[1:L + 1, 2] = 5e-8
+        rows[1:L + 1, 3] = 0.5
+        rows[L + 1] = [0.0, SI_SLD, 5e-8, 3.0]
+        items.append((0, rows, float(rng.uniform(0.9, 1.1)), 1e-7))
+    return _pack("microsliced", [(Q, Robs, err, dq_over_q)], items,
+                 {"L": L, "dz": dz})
+
+
 def random_batch(rng, n_items, L_choices, nq_choices, dqq_choices, n_datasets=None):
     """Small ragged batch for parity tests (shares datasets between items)."""
     n_datasets = n_datasets or max(1, n_items // 2)

@@ -75,7 +75,7 @@ def test_invalid_descriptions_rejected(case):
         elif case == "too_few_rows":
             row_off = [0, 1, 4]
         elif case == "too_many_layers":
-            row_off = [0, 4, 4 + n.NR_MAX_LAYERS + 3]
+            row_off = [0, 4, 4 + n.NR_MAX_DEEP_LAYERS + 3]
         elif case == "bad_dataset":
             dsi = [0, 2]
         d, keep = _desc(n, q_off, dqq, dsi, row_off, prec)
@@ -92,6 +92,8 @@ def test_null_plan_calls_rejected():
     assert L.nr_loglik(None, ctypes.byref(v), None, None, 0, None) == n.NR_EINVAL
     assert L.nr_loglik_grad(None, ctypes.byref(v), None, None, None, None, 0, None) == n.NR_EINVAL
     assert L.nr_reflectivity(None, ctypes.byref(v), None, None, 0, None) == n.NR_EINVAL
+    assert L.nr_loglik_grad_res(None, ctypes.byref(v), None, None, None, None, None, 0,
+                                None) == n.NR_EINVAL
     assert L.nr_plan_destroy(None) == n.NR_OK
 
 

@@ -1,0 +1,213 @@
+"""The HMC driver (nr_hmc_*) against the oracle's transition (oracle/hmc.py):
+the same Philox draws, the leapfrog in unconstrained coordinates through the
+affine, log and logit transforms, the accept decisions, divergences, the
+Welford window and dual averaging; and captured transitions replayed as a
+graph equal to eager ones."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+SEED = 20250906924
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def nr(torch_cuda):
+    import paper_2509_06924_amd as nr
+    return nr
+
+
+def _batch(seed, n_items=4):
+    from paper_2509_06924_amd import inputs
+    rng = np.random.default_rng(seed)
+    return inputs.random_batch(rng, n_items=n_items, L_choices=[1, 2, 3], nq_choices=[30, 70],
+                               dqq_choices=[0.0, 0.05], n_datasets=2)
+
+
+def _transforms(batch):
+    """Per-entry kinds and constants: d in log space, rho_re pre-scaled,
+    rho_im fixed, sigma bounded to (0, 30); scale pre-scaled around 1, bkg in
+    log space; entries the model does not read are FIXED."""
+    from oracle import hmc as oh
+    R = batch.layers.shape[0]
+    kind = np.zeros((R, 4), np.uint8)
+    a = np.zeros((R, 4))
+    b = np.ones((R, 4))
+    for it in range(batch.n_items):
+        r0, r1 = batch.row_off[it], batch.row_off[it + 1]
+        for r in range(r0, r1):
+            front, back = r == r0, r == r1 - 1
+            kind[r, 1] = oh.AFFINE
+            b[r, 1] = 1e-6
+            if not front:
+                kind[r, 3] = oh.LOGIT
+                b[r, 3] = 30.0
+            if not front and not back:
+                kind[r, 0] = oh.LOG
+    kind_i = np.tile(np.array([oh.AFFINE, oh.LOG], np.uint8), (batch.n_items, 1))
+    a_i = np.tile(np.array([1.0, 0.0]), (batch.n_items, 1))
+    b_i = np.tile(np.array([0.01, 1e-7]), (batch.n_items, 1))
+    return kind, a, b, kind_i, a_i, b_i
+
+
+def _inverse_mass(batch):
+    R = batch.layers.shape[0]
+    return np.full((R, 4), 0.05), np.full((batch.n_items, 2), 0.05)
+
+
+def _oracle_chains(orc, batch, steps, inv_mass):
+    from oracle import hmc as oh
+    kind, a, b, kind_i, a_i, b_i = _transforms(batch)
+    im_r, im_i = inv_mass
+    chains = []
+    for c in range(batch.n_items):
+        r0, r1 = batch.row_off[c], batch.row_off[c + 1]
+        Q, Robs, Rerr, dqq = batch.data_of(c)
+        nr_ = r1 - r0
+
+        def target(th, nr_=nr_, Q=Q, Robs=Robs, Rerr=Rerr, dqq=dqq):
+            rows = th[:4 * nr_].reshape(nr_, 4)
+            ll, g, gi = orc.loglik_grad_cs(rows, th[4 * nr_], th[4 * nr_ + 1], Q, Robs, Rerr, dqq)
+            return ll, np.concatenate([g.ravel(), gi])
+
+        theta = np.concatenate([batch.layers[r0:r1].ravel(), [batch.scale[c], batch.bkg[c]]])
+        chains.append(oh.Chain(target, theta,
+                               np.concatenate([kind[r0:r1].ravel(), kind_i[c]]),
+                               np.concatenate([a[r0:r1].ravel(), a_i[c]]),
+                               np.concatenate([b[r0:r1].ravel(), b_i[c]]),
+                               np.concatenate([im_r[r0:r1].ravel(), im_i[c]]),
+                               steps[c], chain_id=c, seed=SEED))
+    return chains
+
+
+def _driver(nr, batch, steps, n_leapfrog):
+    kind, a, b, kind_i, a_i, b_i = _transforms(batch)
+    im_r, im_i = _inverse_mass(batch)
+    prob = nr.Problem.from_batch(batch)
+    return nr.HMC(prob, kind, kind_i, a, b, a_i, b_i, im_r, im_i, step=steps,
+                  n_leapfrog=n_leapfrog, max_energy_error=1000.0, seed=SEED,
+                  target_accept=0.8).init(from_theta=True)
+
+
+def _entries(h, batch, c):
+    r0, r1 = batch.row_off[c], batch.row_off[c + 1]
+    z = np.concatenate([h.z_rows.cpu().numpy()[r0:r1].ravel(), h.z_inst.cpu().numpy()[c]])
+    th = np.concatenate([h.layers.cpu().numpy()[r0:r1].ravel(),
+                         [h.scale.cpu().numpy()[c], h.bkg.cpu().numpy()[c]]])
+    im = np.concatenate([h.inv_mass_rows.cpu().numpy()[r0:r1].ravel(),
+                         h.inv_mass_inst.cpu().numpy()[c]])
+    return z, th, im
+
+
+def _compare(h, chains, batch, what):
+    logL = h.logL.cpu().numpy()
+    U = h.potential.cpu().numpy()
+    acc = h.n_accept.cpu().numpy()
+    div = h.n_divergent.cpu().numpy()
+    ap = h.accept_prob.cpu().numpy()
+    de = h.energy_error.cpu().numpy()
+    step = h.step.cpu().numpy()
+    for c, ch in enumerate(chains):
+        tag = f"{what} chain {c}"
+        assert acc[c] == ch.n_accept and div[c] == ch.n_divergent, tag
+        z, th, im = _entries(h, batch, c)
+        mv = ch.moving
+        assert np.allclose(z[mv], ch.z[mv], rtol=1e-9, atol=1e-12), tag
+        assert np.allclose(th, ch.theta, rtol=1e-9, atol=0), tag
+        assert np.allclose(im, ch.inv_mass, rtol=1e-9, atol=0), tag
+        assert abs(logL[c] - ch.logL) <= 1e-9 * abs(ch.logL), tag
+        assert abs(U[c] - ch.U) <= 1e-9 * max(1.0, abs(ch.U)), tag
+        assert abs(ap[c] - ch.accept_prob) <= 1e-8, tag
+        if np.isfinite(ch.energy_error) and abs(ch.energy_error) < 1e6:
+            assert abs(de[c] - ch.energy_error) <= 1e-8 * max(1.0, abs(ch.energy_error)), tag
+        assert abs(step[c] - ch.step) <= 1e-9 * ch.step, tag
+
+
+@pytest.mark.parametrize("n_leapfrog", [1, 4])
+def test_transitions_match_oracle(nr, orc, n_leapfrog):
+    batch = _batch(910 + n_leapfrog)
+    # the last chain's step is far too long: its transitions diverge
+    steps = np.array([2e-3, 5e-3, 1e-2, 50.0])
+    h = _driver(nr, batch, steps, n_leapfrog)
+    chains = _oracle_chains(orc, batch, steps, _inverse_mass(batch))
+    _compare(h, chains, batch, "init")
+    h.adapt(step_restart=True)
+    for ch in chains:
+        ch.da_restart()
+    for t in range(3):
+        h.transition(adapt_mass=True, adapt_step=True)
+        for ch in chains:
+            ch.transition(n_leapfrog, max_error=1000.0, adapt_mass=True, adapt_step=True,
+                          target_accept=0.8)
+        _compare(h, chains, batch, f"transition {t}")
+    assert h.n_divergent.cpu().numpy()[3] >= 1
+    assert h.n_accept.cpu().numpy()[:3].sum() >= 1
+    h.adapt(mass_window_end=True, step_final=True)
+    for ch in chains:
+        ch.mass_window_end()
+        ch.da_final()
+    _compare(h, chains, batch, "window end")
+    # and sampling continues from the adapted metric and step
+    h.transition()
+    for ch in chains:
+        ch.transition(n_leapfrog, max_error=1000.0)
+    _compare(h, chains, batch, "after adaptation")
+
+
+def test_graph_replays_equal_eager(nr, torch_cuda):
+    torch = torch_cuda
+    batch = _batch(930, n_items=6)
+    steps = np.full(6, 4e-3)
+    eager = _driver(nr, batch, steps, 3)
+    graphed = _driver(nr, batch, steps, 3)
+    eager.adapt(step_restart=True)
+    graphed.adapt(step_restart=True)
+    g = graphed.graph(n_transitions=1, adapt_mass=True, adapt_step=True)
+    scratch = torch.zeros(1000, dtype=torch.float64, device=eager.layers.device)
+    for k in range(4):
+        eager.transition(adapt_mass=True, adapt_step=True)
+        g.launch()
+        scratch.add_(1.0)  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        for name in ("z_rows", "z_inst", "layers", "scale", "bkg", "logL", "g_rows", "g_inst",
+                     "potential", "accept_prob", "energy_error", "n_accept", "n_divergent",
+                     "step"):
+            a, b = getattr(eager, name), getattr(graphed, name)
+            if a.dtype == torch.float64:  # bitwise, so that equal NaNs compare equal
+                a, b = a.view(torch.int64), b.view(torch.int64)
+            assert torch.equal(a, b), (k, name)
+    g.close()
+
+
+def test_fixed_and_unread_entries_never_move(nr):
+    batch = _batch(940)
+    steps = np.full(4, 3e-3)
+    h = _driver(nr, batch, steps, 3)
+    before = h.layers.clone()
+    for _ in range(3):
+        h.transition()
+    kind, *_ = _transforms(batch)
+    fixed = kind == 0
+    after = h.layers.cpu().numpy()
+    assert np.array_equal(after[fixed], before.cpu().numpy()[fixed])
+    assert np.any(after[~fixed] != before.cpu().numpy()[~fixed])
+
+
+def test_invalid_configuration_rejected(nr):
+    import ctypes
+    from paper_2509_06924_amd import _native as n
+    batch = _batch(950, n_items=2)
+    prob = nr.Problem.from_batch(batch)
+    h = ctypes.c_void_p()
+    for cfg in (n.HmcConfig(0, 1000.0, 1, 0.8), n.HmcConfig(5, 1000.0, 1, 1.0),
+                n.HmcConfig(5, -1.0, 1, 0.8)):
+        assert n.lib().nr_hmc_create(prob.plan.handle, ctypes.byref(cfg),
+                                     ctypes.byref(h)) == n.NR_EINVAL

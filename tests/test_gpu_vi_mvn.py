@@ -1,0 +1,156 @@
+"""The full-rank Gaussian VI driver (nr_vi_mvn_*) against the oracle
+(oracle/vi_fullrank.py): the same Philox draws, the per-restart ELBO and its
+gradient through the transforms, Adam steps over several iterations; graph
+replays equal eager steps."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+SEED = 4242
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def nr(torch_cuda):
+    import paper_2509_06924_amd as nr
+    return nr
+
+
+def _setup(R, S, L, nq, dqq, seed):
+    """A template stack of L layers and one dataset; R x S items."""
+    from paper_2509_06924_amd import inputs
+    from oracle import hmc as oh
+    rng = np.random.default_rng(seed)
+    template = inputs.random_batch(rng, n_items=1, L_choices=[L], nq_choices=[nq],
+                                   dqq_choices=[dqq], n_datasets=1)
+    rows = template.rows_of(0)
+    Q, Robs, Rerr, dq = template.data_of(0)
+    items = [(0, rows, template.scale[0], template.bkg[0])] * (R * S)
+    batch = inputs._pack("mvn", [(Q, Robs, Rerr, dq)], items, {})
+    nrow = rows.shape[0]
+    P = 4 * nrow + 2
+    kind = np.zeros(P, np.uint8)
+    a = np.zeros(P)
+    b = np.ones(P)
+    for r in range(nrow):
+        front, back = r == 0, r == nrow - 1
+        kind[4 * r + 1] = oh.AFFINE
+        b[4 * r + 1] = 1e-6
+        if not front:
+            kind[4 * r + 3] = oh.LOGIT
+            b[4 * r + 3] = 30.0
+        if not front and not back:
+            kind[4 * r] = oh.LOG
+    kind[P - 2], a[P - 2], b[P - 2] = oh.AFFINE, 1.0, 0.01
+    kind[P - 1], b[P - 1] = oh.LOG, 1e-7
+    theta = np.concatenate([rows.ravel(), [template.scale[0], template.bkg[0]]])
+    moving = kind != oh.FIXED
+    z0 = np.zeros(P)
+    for p in np.flatnonzero(moving):
+        z0[p] = oh.inverse_transform(kind[p], a[p], b[p], theta[p])
+    mu = np.tile(z0, (R, 1)) + 0.05 * rng.standard_normal((R, P)) * moving
+    return batch, (Q, Robs, Rerr, dq), nrow, kind, a, b, theta, mu
+
+
+def _oracle(orc, data, nrow, kind, a, b, theta, mu, sigma0):
+    from oracle import vi_fullrank as vf
+    Q, Robs, Rerr, dq = data
+    moving = kind != 0
+    idx = np.flatnonzero(moving)
+
+    def target(th_m):
+        th = theta.copy()
+        th[idx] = th_m
+        ll, g, gi = orc.loglik_grad_cs(th[:4 * nrow].reshape(nrow, 4), th[-2], th[-1], Q, Robs,
+                                       Rerr, dq)
+        return ll, np.concatenate([g.ravel(), gi])[idx]
+
+    restarts = [vf.Restart(mu[r][idx], sigma0, kind[idx], a[idx], b[idx])
+                for r in range(mu.shape[0])]
+    return restarts, target, idx
+
+
+def _oracle_step(restarts, target, idx, P, S, it, lr):
+    from oracle import vi_fullrank as vf
+    out = []
+    for r, rs in enumerate(restarts):
+        eps = np.stack([vf.draws(SEED, it, r * S + s, P)[idx] for s in range(S)])
+        elbo, g = rs.elbo_grad(eps, target)
+        rs.adam_step(g, lr)
+        out.append((elbo, g))
+    return out
+
+
+@pytest.mark.parametrize("R,S,L", [(3, 4, 2), (2, 8, 5)])
+def test_steps_match_oracle(nr, orc, R, S, L):
+    batch, data, nrow, kind, a, b, theta, mu = _setup(R, S, L, 50, 0.05, 960 + L)
+    prob = nr.Problem.from_batch(batch)
+    vi = nr.MvnVI(prob, R, S, kind, a, b, theta, mu=mu, sigma0=0.1, lr=0.05, seed=SEED)
+    restarts, target, idx = _oracle(orc, data, nrow, kind, a, b, theta, mu, 0.1)
+    P = kind.size
+    for it in range(3):
+        vi.step(adam=True)
+        ref = _oracle_step(restarts, target, idx, P, S, it, 0.05)
+        elbo = vi.elbo.cpu().numpy()
+        gmu = vi.grad_mu.cpu().numpy()
+        gom = vi.grad_omega.cpu().numpy()
+        glam = vi.grad_lam.cpu().numpy()
+        mu_d = vi.mu.cpu().numpy()
+        om_d = vi.omega.cpu().numpy()
+        lam_d = vi.lam.cpu().numpy()
+        for r, rs in enumerate(restarts):
+            e_o, g_o = ref[r]
+            tag = f"step {it} restart {r}"
+            assert abs(elbo[r] - e_o) <= 1e-9 * max(1.0, abs(e_o)), tag
+            scale = max(np.max(np.abs(g_o["mu"])), np.max(np.abs(g_o["omega"])),
+                        np.max(np.abs(g_o["lam"])))
+            assert np.max(np.abs(gmu[r][idx] - g_o["mu"])) <= 1e-8 * scale, tag
+            assert np.max(np.abs(gom[r][idx] - g_o["omega"])) <= 1e-8 * scale, tag
+            assert np.max(np.abs(glam[r][np.ix_(idx, idx)] - g_o["lam"])) <= 1e-8 * scale, tag
+            # Adam normalises each step to about lr: parameters agree closely
+            assert np.allclose(mu_d[r][idx], rs.mu, rtol=1e-9, atol=1e-9), tag
+            assert np.allclose(om_d[r][idx], rs.omega, rtol=1e-9, atol=1e-9), tag
+            assert np.allclose(np.tril(lam_d[r][np.ix_(idx, idx)], -1), rs.lam, atol=1e-9), tag
+        fixed = np.flatnonzero(kind == 0)
+        assert np.all(gmu[:, fixed] == 0) and np.all(gom[:, fixed] == 0)
+
+
+def test_graph_replays_equal_eager(nr, torch_cuda):
+    torch = torch_cuda
+    R, S = 2, 4
+    batch, data, nrow, kind, a, b, theta, mu = _setup(R, S, 3, 40, 0.0, 990)
+    pa = nr.Problem.from_batch(batch)
+    pb = nr.Problem.from_batch(batch)
+    va = nr.MvnVI(pa, R, S, kind, a, b, theta, mu=mu, seed=SEED)
+    vb = nr.MvnVI(pb, R, S, kind, a, b, theta, mu=mu, seed=SEED)
+    g = vb.graph(n_steps=2)
+    for k in range(3):
+        va.step()
+        va.step()
+        g.launch()
+        torch.cuda.synchronize()
+        for name in ("mu", "omega", "lam", "elbo", "grad_mu", "grad_omega", "grad_lam"):
+            x, y = getattr(va, name), getattr(vb, name)
+            assert torch.equal(x.view(torch.int64), y.view(torch.int64)), (k, name)
+    g.close()
+
+
+def test_invalid_configuration_rejected(nr):
+    import ctypes
+    from paper_2509_06924_amd import _native as n
+    batch, *_ = _setup(2, 3, 2, 20, 0.0, 995)
+    prob = nr.Problem.from_batch(batch)
+    h = ctypes.c_void_p()
+    for cfg in (n.MvnConfig(2, 4, 0.05, 0.9, 0.999, 1e-8, 0),   # R S != items
+                n.MvnConfig(2, 3, 0.0, 0.9, 0.999, 1e-8, 0),
+                n.MvnConfig(2, 3, 0.05, 1.0, 0.999, 1e-8, 0)):
+        assert n.lib().nr_vi_mvn_create(prob.plan.handle, ctypes.byref(cfg),
+                                        ctypes.byref(h)) == n.NR_EINVAL
