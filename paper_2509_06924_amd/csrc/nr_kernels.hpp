@@ -861,8 +861,10 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(K
   flag(a.item_status, u.item, bits);
 
   const int NR = N + 2;
-  // record of 4 + 4 NR doubles; the last field only in the RES form
-  const int nf = (RES ? 4 : 3) + 4 * NR;
+  // record of 4 + 4 NR doubles; the last field is the resolution sum (0
+  // outside the RES form, written all the same so that the records of
+  // consecutive units form one contiguous store)
+  const int nf = 4 + 4 * NR;
   if constexpr (TAIL) {
     // Lanes of one item are contiguous; idle lanes (key -1) follow the last
     // item.  A segmented inclusive scan over the lanes leaves each item's
@@ -900,7 +902,10 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(K
         seg_put(3 + 3 * NR + m, fac * acc.Hs[m]);
       }
     }
-    if constexpr (RES) seg_put(3 + 4 * NR, fac * Hq);
+    if constexpr (RES)
+      seg_put(3 + 4 * NR, fac * Hq);
+    else if (writer)
+      rec[3 + 4 * NR] = 0.0;
     return;
   }
   // ---- wave reduction; the sums go through LDS into one coalesced store ----
@@ -931,6 +936,8 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(K
   if constexpr (RES) {
     const double hq = wave_sum(fac * Hq);
     if (lane == 0) stage[3 + 4 * NR] = hq;
+  } else {
+    if (lane == 0) stage[3 + 4 * NR] = 0.0;
   }
   __syncthreads();
   double* rec = a.rec + a.wu_rec[w];

@@ -15,8 +15,9 @@
 //      the cotangent of the state leaving the chunk at its top, V_l^H c_0
 //      (the cotangent of a linear map's input is its conjugate transpose
 //      applied to the output's cotangent);
-//   3. the lane's own forward sweep from its entering state (the state tape
-//      in LDS) and the level-by-level adjoint of the shallow kernels.
+//   3. the lane's own forward sweep from its entering state (the state tape,
+//      in registers or LDS) and the level-by-level adjoint of the shallow
+//      kernels.
 // A medium at a chunk boundary receives cotangent contributions from two
 // lanes; the lower lane's part is kept in an extra slot and added to the
 // upper lane's slot before the record is written.  Every level's arithmetic
@@ -81,15 +82,35 @@ __device__ __forceinline__ Lvl level_coeffs(const MathTables& T, const Layers<F6
 
 }  // namespace
 
-// Dynamic LDS: the state tape [ch_max][4][64] (P re, P im, Qv re, Qv im of
-// the state entering each of the lane's levels), then the accumulators
-// [ch_max + 1][4][64] (Hw re, Hw im, Hd, Hs per medium slot; slot t is medium
-// lo + t, the last used slot is the lane's lower boundary medium).
-template <bool RES>
-__global__ __launch_bounds__(64) void k_loglik_grad_scan(KernelArgs a, int ch_max) {
+// Per-lane storage of the state tape (the state entering each of the lane's
+// levels) and of the accumulators (Hw re, Hw im, Hd, Hs per medium slot; slot
+// t is medium lo + t, slot n = hi - lo the lane's lower boundary medium):
+// registers where they fit, else LDS in lane-interleaved planes.
+template <int CHT, bool IN_LDS>
+struct LaneTape {
+  double r[IN_LDS ? 1 : CHT][4];
+  __device__ __forceinline__ double& at(double* lds, int lane, int t, int f) {
+    if constexpr (IN_LDS)
+      return lds[(t * 4 + f) * 64 + lane];
+    else
+      return r[t][f];
+  }
+};
+
+// CHT: the largest levels-per-lane the launch's items need (1 .. 32).
+template <int CHT, bool RES>
+__global__ __launch_bounds__(64) void k_loglik_grad_scan(KernelArgs a) {
+  constexpr bool kTapeLds = CHT >= 8;
+  constexpr bool kAccLds = CHT >= 32;
   __shared__ Shared s;
-  extern __shared__ double dyn[];
+  __shared__ double tape_lds[kTapeLds ? CHT * 4 * 64 : 1];
+  __shared__ double acc_lds[kAccLds ? (CHT + 1) * 4 * 64 : 1];
+  LaneTape<CHT, kTapeLds> tape;
+  LaneTape<CHT + 1, kAccLds> accs;
   const int lane = threadIdx.x;
+  auto TP = [&](int t, int f) -> double& { return tape.at(tape_lds, lane, t, f); };
+  auto AC = [&](int t, int f) -> double& { return accs.at(acc_lds, lane, t, f); };
+
   const int w = blockIdx.x;
   const int item = a.wu_item[w];
   const int ds = a.dataset_of_item[item];
@@ -100,13 +121,12 @@ __global__ __launch_bounds__(64) void k_loglik_grad_scan(KernelArgs a, int ch_ma
   const int NL = N + 1;  // levels 0..N
   const int CH = (NL + 63) / 64;
   const int lo = min(lane * CH, NL), hi = min(lo + CH, NL);
-  const bool own = lo < hi;
+  const int n = hi - lo;  // levels of this lane (0 .. CH <= CHT)
+  const bool own = n > 0;
   stage_shared(s, lane, a.rule);
-  double* tape = dyn;
-  double* acc = dyn + (size_t)ch_max * 4 * 64;
-  auto TP = [&](int t, int f) -> double& { return tape[(t * 4 + f) * 64 + lane]; };
-  auto AC = [&](int t, int f) -> double& { return acc[(t * 4 + f) * 64 + lane]; };
-  for (int t = 0; t <= CH; ++t)
+#pragma unroll
+  for (int t = 0; t <= CHT; ++t)
+#pragma unroll
     for (int f = 0; f < 4; ++f) AC(t, f) = 0.0;
 
   const double Q = a.q[qoff + i];
@@ -133,15 +153,19 @@ __global__ __launch_bounds__(64) void k_loglik_grad_scan(KernelArgs a, int ch_ma
     M2 X = m2_identity();
     if (own) {
       cd kzn = medium_root(L, kz0sq, hi).kz;
-      for (int jj = hi - 1; jj >= lo; --jj) {
-        const cd kzc = (jj == 0) ? kz0 : medium_root(L, kz0sq, jj).kz;
-        const Lvl lv = level_coeffs(s.tab, L, jj, kzc, kzn);
-        const cd a0 = X.a + lv.it.rp * X.c, b0 = X.b + lv.it.rp * X.d;
-        X.c = lv.e * (lv.it.rp * X.a + X.c);
-        X.d = lv.e * (lv.it.rp * X.b + X.d);
-        X.a = a0;
-        X.b = b0;
-        kzn = kzc;
+#pragma unroll
+      for (int t = CHT - 1; t >= 0; --t) {
+        if (t < n) {
+          const int jj = lo + t;
+          const cd kzc = (jj == 0) ? kz0 : medium_root(L, kz0sq, jj).kz;
+          const Lvl lv = level_coeffs(s.tab, L, jj, kzc, kzn);
+          const cd a0 = X.a + lv.it.rp * X.c, b0 = X.b + lv.it.rp * X.d;
+          X.c = lv.e * (lv.it.rp * X.a + X.c);
+          X.d = lv.e * (lv.it.rp * X.b + X.d);
+          X.a = a0;
+          X.b = b0;
+          kzn = kzc;
+        }
       }
     }
     // 2. suffix and prefix scans across the lanes
@@ -178,18 +202,22 @@ __global__ __launch_bounds__(64) void k_loglik_grad_scan(KernelArgs a, int ch_ma
     {
       cd Pv = Ps, Qv = Qs;
       cd kzn = medium_root(L, kz0sq, hi, edge).kz;
-      for (int jj = hi - 1; jj >= lo; --jj) {
-        TP(jj - lo, 0) = Pv.re;
-        TP(jj - lo, 1) = Pv.im;
-        TP(jj - lo, 2) = Qv.re;
-        TP(jj - lo, 3) = Qv.im;
-        const cd kzc = (jj == 0) ? kz0 : medium_root(L, kz0sq, jj, edge).kz;
-        const Lvl lv = level_coeffs(s.tab, L, jj, kzc, kzn);
-        const cd Pn = Pv + lv.it.rp * Qv;
-        const cd t = lv.it.rp * Pv + Qv;
-        Qv = (jj >= 1) ? lv.e * t : t;
-        Pv = Pn;
-        kzn = kzc;
+#pragma unroll
+      for (int t = CHT - 1; t >= 0; --t) {
+        if (t < n) {
+          const int jj = lo + t;
+          TP(t, 0) = Pv.re;
+          TP(t, 1) = Pv.im;
+          TP(t, 2) = Qv.re;
+          TP(t, 3) = Qv.im;
+          const cd kzc = (jj == 0) ? kz0 : medium_root(L, kz0sq, jj, edge).kz;
+          const Lvl lv = level_coeffs(s.tab, L, jj, kzc, kzn);
+          const cd Pn = Pv + lv.it.rp * Qv;
+          const cd tt = lv.it.rp * Pv + Qv;
+          Qv = (jj >= 1) ? lv.e * tt : tt;
+          Pv = Pn;
+          kzn = kzc;
+        }
       }
     }
     double sw = 0.0;
@@ -201,42 +229,46 @@ __global__ __launch_bounds__(64) void k_loglik_grad_scan(KernelArgs a, int ch_ma
       rc = medium_root(L, kz0sq, lo);
     }
     cd kzbc = mk(0.0, 0.0);
-    for (int jj = lo; jj < hi; ++jj) {
-      const RootT<double> rn = medium_root(L, kz0sq, jj + 1);
-      const Lvl lv = level_coeffs(s.tab, L, jj, rc.kz, rn.kz);
-      const cd Pt = mk(TP(jj - lo, 0), TP(jj - lo, 1));
-      const cd Qt = mk(TP(jj - lo, 2), TP(jj - lo, 3));
-      const bool ph = jj >= 1;
-      const AdjStep<double> st =
-          adjoint_step(Pt, Qt, Pb, Qb, rc.kz, rn.kz, lv.it, lv.C, ph, lv.e, lv.D);
-      kzbc += st.kzb_c;
-      if constexpr (RES)
-        if (jj == 0) Hq = fma(0.5 * dq_dres * tk, kzbc.re, Hq);
-      {
-        double hs = AC(jj + 1 - lo, 3);
-        acc_re_dot(hs, st.ub, lv.it.kk);
-        AC(jj + 1 - lo, 3) = hs;
+#pragma unroll
+    for (int t = 0; t < CHT; ++t) {
+      if (t < n) {
+        const int jj = lo + t;
+        const RootT<double> rn = medium_root(L, kz0sq, jj + 1);
+        const Lvl lv = level_coeffs(s.tab, L, jj, rc.kz, rn.kz);
+        const cd Pt = mk(TP(t, 0), TP(t, 1));
+        const cd Qt = mk(TP(t, 2), TP(t, 3));
+        const bool ph = jj >= 1;
+        const AdjStep<double> st =
+            adjoint_step(Pt, Qt, Pb, Qb, rc.kz, rn.kz, lv.it, lv.C, ph, lv.e, lv.D);
+        kzbc += st.kzb_c;
+        if constexpr (RES)
+          if (jj == 0) Hq = fma(0.5 * dq_dres * tk, kzbc.re, Hq);
+        {
+          double hs = AC(t + 1, 3);
+          acc_re_dot(hs, st.ub, lv.it.kk);
+          AC(t + 1, 3) = hs;
+        }
+        if (ph) {
+          double hd = AC(t, 2);
+          acc_dd(hd, rc.kz, st.w);
+          AC(t, 2) = hd;
+          cd hw = mk(AC(t, 0), AC(t, 1));
+          acc_wbar<RES>(hw, sw, rc.kz, rc.inv_abs2, kzbc);
+          AC(t, 0) = hw.re;
+          AC(t, 1) = hw.im;
+        }
+        Pb = st.Pb;
+        Qb = st.Qb;
+        kzbc = st.kzb_n;
+        rc = rn;
+        if (t == n - 1) {
+          // this lane's part of its lower boundary medium (hi), from level hi - 1
+          cd hw = mk(AC(t + 1, 0), AC(t + 1, 1));
+          acc_wbar<RES>(hw, sw, rc.kz, rc.inv_abs2, kzbc);
+          AC(t + 1, 0) = hw.re;
+          AC(t + 1, 1) = hw.im;
+        }
       }
-      if (ph) {
-        double hd = AC(jj - lo, 2);
-        acc_dd(hd, rc.kz, st.w);
-        AC(jj - lo, 2) = hd;
-        cd hw = mk(AC(jj - lo, 0), AC(jj - lo, 1));
-        acc_wbar<RES>(hw, sw, rc.kz, rc.inv_abs2, kzbc);
-        AC(jj - lo, 0) = hw.re;
-        AC(jj - lo, 1) = hw.im;
-      }
-      Pb = st.Pb;
-      Qb = st.Qb;
-      kzbc = st.kzb_n;
-      rc = rn;
-    }
-    {
-      // this lane's part of the lower boundary medium (hi), from level hi - 1
-      cd hw = mk(AC(hi - lo, 0), AC(hi - lo, 1));
-      acc_wbar<RES>(hw, sw, rc.kz, rc.inv_abs2, kzbc);
-      AC(hi - lo, 0) = hw.re;
-      AC(hi - lo, 1) = hw.im;
     }
     if constexpr (RES) Hq = fma(0.5 * q * dq_dres * tk, sw, Hq);
   }
@@ -263,28 +295,33 @@ __global__ __launch_bounds__(64) void k_loglik_grad_scan(KernelArgs a, int ch_ma
 
   // ---- the record: boundary slots join the next lane's first medium ----
   double* rec = a.rec + a.wu_rec[w];
-  const int bslot = own ? hi - lo : 0;
-  double from_above[4];
+  double bnd[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int t = 1; t <= CHT; ++t)
+    if (t == n)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) bnd[f] = AC(t, f);
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
-    const double v = own ? AC(bslot, f) : 0.0;
-    from_above[f] = __shfl(v, lane > 0 ? lane - 1 : 0, 64);
+    const double from_above = __shfl(bnd[f], lane > 0 ? lane - 1 : 0, 64);
+    if (own && lane > 0) AC(0, f) += from_above;
   }
-  if (own && lane > 0)
-    for (int f = 0; f < 4; ++f) AC(0, f) += from_above[f];
   if (own) {
-    for (int t = 0; t < hi - lo; ++t) {
-      const int m = lo + t;
-      rec[3 + m] = fac * AC(t, 0);
-      rec[3 + NR + m] = fac * AC(t, 1);
-      rec[3 + 2 * NR + m] = fac * AC(t, 2);
-      rec[3 + 3 * NR + m] = fac * AC(t, 3);
+#pragma unroll
+    for (int t = 0; t < CHT; ++t) {
+      if (t < n) {
+        const int m = lo + t;
+        rec[3 + m] = fac * AC(t, 0);
+        rec[3 + NR + m] = fac * AC(t, 1);
+        rec[3 + 2 * NR + m] = fac * AC(t, 2);
+        rec[3 + 3 * NR + m] = fac * AC(t, 3);
+      }
     }
     if (hi == NL) {  // the backing medium N + 1
-      rec[3 + NL] = fac * AC(bslot, 0);
-      rec[3 + NR + NL] = fac * AC(bslot, 1);
-      rec[3 + 2 * NR + NL] = fac * AC(bslot, 2);
-      rec[3 + 3 * NR + NL] = fac * AC(bslot, 3);
+      rec[3 + NL] = fac * bnd[0];
+      rec[3 + NR + NL] = fac * bnd[1];
+      rec[3 + 2 * NR + NL] = fac * bnd[2];
+      rec[3 + 3 * NR + NL] = fac * bnd[3];
     }
   }
   const double hq = RES ? wave_sum(Hq) : 0.0;
@@ -296,27 +333,46 @@ __global__ __launch_bounds__(64) void k_loglik_grad_scan(KernelArgs a, int ch_ma
   }
 }
 
+// The kernel instance for a launch: levels-per-lane rounded up to a power of
+// two (register tape up to 4, register accumulators up to 16).
+static int scan_cht(int ch_max) {
+  int c = 1;
+  while (c < ch_max) c <<= 1;
+  return c;
+}
+
 size_t scan_lds_bytes(int ch_max) {
-  return sizeof(double) * ((size_t)ch_max * 4 * 64 + (size_t)(ch_max + 1) * 4 * 64);
+  const int c = scan_cht(ch_max);
+  size_t b = sizeof(Shared);
+  if (c >= 8) b += sizeof(double) * (size_t)c * 4 * 64;
+  if (c >= 32) b += sizeof(double) * (size_t)(c + 1) * 4 * 64;
+  return b;
 }
 
 hipError_t prepare_grad_scan(int ch_max) {
-  const int bytes = (int)scan_lds_bytes(ch_max);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_loglik_grad_scan<false>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_loglik_grad_scan<true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  return e;
+  // static LDS only; the instances exist up to 32 levels per lane
+  return (ch_max >= 1 && scan_cht(ch_max) <= kScanMaxChunk) ? hipSuccess : hipErrorInvalidValue;
+}
+
+template <int CHT>
+static void launch_scan_cht(bool res, const KernelArgs& a, int n_wu, hipStream_t st) {
+  if (res)
+    hipLaunchKernelGGL((k_loglik_grad_scan<CHT, true>), dim3(n_wu), dim3(64), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_loglik_grad_scan<CHT, false>), dim3(n_wu), dim3(64), 0, st, a);
 }
 
 hipError_t launch_grad_scan(bool res, int ch_max, const KernelArgs& a, int n_wu, hipStream_t st) {
   if (n_wu <= 0) return hipSuccess;
-  const size_t lds = scan_lds_bytes(ch_max);
-  if (res)
-    hipLaunchKernelGGL(k_loglik_grad_scan<true>, dim3(n_wu), dim3(64), lds, st, a, ch_max);
-  else
-    hipLaunchKernelGGL(k_loglik_grad_scan<false>, dim3(n_wu), dim3(64), lds, st, a, ch_max);
+  switch (scan_cht(ch_max)) {
+    case 1: launch_scan_cht<1>(res, a, n_wu, st); break;
+    case 2: launch_scan_cht<2>(res, a, n_wu, st); break;
+    case 4: launch_scan_cht<4>(res, a, n_wu, st); break;
+    case 8: launch_scan_cht<8>(res, a, n_wu, st); break;
+    case 16: launch_scan_cht<16>(res, a, n_wu, st); break;
+    case 32: launch_scan_cht<32>(res, a, n_wu, st); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -95,6 +95,29 @@ def test_null_plan_calls_rejected():
     assert L.nr_loglik_grad_res(None, ctypes.byref(v), None, None, None, None, None, 0,
                                 None) == n.NR_EINVAL
     assert L.nr_plan_destroy(None) == n.NR_OK
+    # the drivers around the gradient
+    h = ctypes.c_void_p()
+    cfg = n.HmcConfig(5, 1000.0, 1, 0.8)
+    assert L.nr_hmc_create(None, ctypes.byref(cfg), ctypes.byref(h)) == n.NR_EINVAL
+    assert not h.value
+    ch = n.HmcChains()
+    assert L.nr_hmc_init(None, ctypes.byref(v), ctypes.byref(ch), 1, None, 0, None) == n.NR_EINVAL
+    assert L.nr_hmc_transition(None, ctypes.byref(v), ctypes.byref(ch), 0, None, 0,
+                               None) == n.NR_EINVAL
+    assert L.nr_hmc_adapt(None, ctypes.byref(ch), 1, None) == n.NR_EINVAL
+    assert L.nr_hmc_destroy(None) == n.NR_OK
+    mcfg = n.MvnConfig(2, 3, 0.05, 0.9, 0.999, 1e-8, 0)
+    assert L.nr_vi_mvn_create(None, ctypes.byref(mcfg), ctypes.byref(h)) == n.NR_EINVAL
+    prm = n.MvnParams()
+    assert L.nr_vi_mvn_step(None, ctypes.byref(v), ctypes.byref(prm), 1, None, 0,
+                            None) == n.NR_EINVAL
+    assert L.nr_vi_mvn_destroy(None) == n.NR_OK
+    g = ctypes.c_void_p()
+    assert L.nr_hmc_graph_create(None, ctypes.byref(v), ctypes.byref(ch), 0, 1, None, 0,
+                                 ctypes.byref(g)) == n.NR_EINVAL
+    assert L.nr_vi_mvn_graph_create(None, ctypes.byref(v), ctypes.byref(prm), 1, None, 0,
+                                    ctypes.byref(g)) == n.NR_EINVAL
+    assert not g.value
 
 
 def test_paper_parameter_dict_packs_to_rows():
