@@ -160,7 +160,12 @@ nr_status nr_plan_create(const nr_batch_desc* desc, nr_plan** plan_out);
  *   xcd_run: consecutive work units of the cost-ordered list given to one of
  *     the 8 XCDs (1..64; the default 8 keeps an item's units in one L2).
  *   pack_tails: 1 packs the trailing partial point groups of several items
- *     of equal depth into one wave (default); 0 gives each its own wave. */
+ *     of equal depth into one wave (default); 0 gives each its own wave.
+ *   split_tails: 1 (default) gives the trailing partial group of a smeared
+ *     item (at least 4 points) a wave of its own whose lanes split the
+ *     smearing nodes (lane = node group x point), when that fills at least 48
+ *     of the 64 lanes; the item's layer records are then wave-uniform.  Other
+ *     tails follow pack_tails.  0: every tail follows pack_tails. */
 #define NR_NUM_BUCKETS 16
 #define NR_VARIANT_AUTO 0
 #define NR_VARIANT_STORE 1
@@ -169,10 +174,11 @@ typedef struct nr_plan_options {
   int32_t grad_variant[NR_NUM_BUCKETS];
   int32_t xcd_run;
   int32_t pack_tails;
+  int32_t split_tails;
 } nr_plan_options;
 
 /* Fills *opts with the defaults (all NR_VARIANT_AUTO, xcd_run 8,
- * pack_tails 1).  NR_EINVAL for NULL. */
+ * pack_tails 1, split_tails 1).  NR_EINVAL for NULL. */
 nr_status nr_plan_options_default(nr_plan_options* opts);
 
 /* Largest layer count L of bucket k (0 <= k < NR_NUM_BUCKETS): items with

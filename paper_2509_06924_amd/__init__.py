@@ -58,6 +58,8 @@ def plan_options(options=None):
         o.xcd_run = int(options["xcd_run"])
     if "pack_tails" in options:
         o.pack_tails = int(options["pack_tails"])
+    if "split_tails" in options:
+        o.split_tails = int(options["split_tails"])
     return o
 
 
@@ -67,7 +69,8 @@ class Plan:
     def __init__(self, q_off, dq_over_q, dataset_of_item, row_off, precision=NR_F64,
                  options=None):
         """options: None (defaults) or a dict with any of grad_variant (list of
-        NR_NUM_BUCKETS ints or {bucket_lmax: variant}), xcd_run, pack_tails."""
+        NR_NUM_BUCKETS ints or {bucket_lmax: variant}), xcd_run, pack_tails,
+        split_tails."""
         self.q_off = np.ascontiguousarray(q_off, np.int64)
         self.dq_over_q = np.ascontiguousarray(dq_over_q, np.float64)
         self.dataset_of_item = np.ascontiguousarray(dataset_of_item, np.int32)

@@ -49,6 +49,7 @@ class PlanOptions(ctypes.Structure):
         ("grad_variant", ctypes.c_int32 * NR_NUM_BUCKETS),
         ("xcd_run", ctypes.c_int32),
         ("pack_tails", ctypes.c_int32),
+        ("split_tails", ctypes.c_int32),
     ]
 
 

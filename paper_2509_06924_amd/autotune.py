@@ -3,7 +3,8 @@
 The library offers equivalent schedules of the same computation
 (`nr_plan_options` in include/nr.h): per layer-count bucket, the store or the
 recompute form of the gradient kernel; the length of the runs of work units
-given to one XCD; packing of the trailing partial point groups.  Which is
+given to one XCD; packing of the trailing partial point groups, or a wave of
+their own with the lanes split over smearing-node groups.  Which is
 fastest depends on the batch (depth mix, points per item, number of items)
 and the precision.  `tune` times `nr_loglik_grad` on the caller's own data
 under candidate schedules (coordinate search, CUDA events on the current
@@ -133,7 +134,7 @@ def tune(batch, precision=_n.NR_F64, device="cuda", cache=None, reps=7, verbose=
     L = np.diff(np.asarray(batch.row_off)) - 2
     used = sorted(set(int(lm[k]) for k in np.searchsorted(lm, L) if k < len(lm))) if L.size else []
     smax = int(_n.lib().nr_store_max_layers(precision))
-    best = {"grad_variant": {}, "xcd_run": 8, "pack_tails": 1}
+    best = {"grad_variant": {}, "xcd_run": 8, "pack_tails": 1, "split_tails": 1}
     best_t = _time_call(problem(best), out, reps)
     trials = [(dict(best), best_t)]
 
@@ -160,6 +161,7 @@ def tune(batch, precision=_n.NR_F64, device="cuda", cache=None, reps=7, verbose=
         if run != best["xcd_run"]:
             consider({**best, "xcd_run": run})
     consider({**best, "pack_tails": 1 - best["pack_tails"]})
+    consider({**best, "split_tails": 1 - best["split_tails"]})
 
     # confirm against the default, interleaved so that drift cancels
     if best != trials[0][0]:

@@ -93,9 +93,11 @@ struct Launch {
   int bucket = 0;
   bool store = false;  // gradient: store variant (else recompute)
   bool tail = false;
-  int scan_ch = 0;  // deep list: the largest levels-per-lane of its items
+  bool split = false;  // split tail units (one item's partial group, lanes over node groups)
+  int scan_ch = 0;     // deep list: the largest levels-per-lane of its items
   int n_wu = 0;
   int32_t* item = nullptr;      // [n_wu]: the unit's item (first item for tails)
+  int32_t* split_code = nullptr;  // [n_wu] split units: points | node groups << 16
   int32_t* p0 = nullptr;        // [n_wu]: first point (full units)
   int64_t* rec = nullptr;       // [n_wu]: record offset (full units)
   int32_t* lane_item = nullptr; // [n_wu * 64] (tail units)
@@ -266,17 +268,19 @@ nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st, b
     a.wu_item = L.item;
     a.wu_p0 = L.p0;
     a.wu_rec = L.rec;
+    a.wu_split = L.split_code;
     a.tail_item = L.lane_item;
     a.tail_pt = L.lane_pt;
     a.tail_rec = L.lane_rec;
     const int form = res ? kFormRecomputeRes : L.store ? kFormStore : kFormRecompute;
+    const int mode = L.tail ? kModeTail : L.split ? kModeSplit : kModeFull;
     hipError_t e;
     if (!grad)
       e = launch_forward(p->precision, op, a, L.n_wu, st);
     else if (L.bucket == kDeepBucket)
       e = launch_grad_scan(res, L.scan_ch, a, L.n_wu, st);
     else
-      e = launch_grad(p->precision, L.bucket, form, L.tail, a, L.n_wu, st);
+      e = launch_grad(p->precision, L.bucket, form, mode, a, L.n_wu, st);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
   }
   if (events && p->ev_stop) {
@@ -574,6 +578,7 @@ nr_status nr_plan_options_default(nr_plan_options* o) {
   for (int k = 0; k < NR_NUM_BUCKETS; ++k) o->grad_variant[k] = NR_VARIANT_AUTO;
   o->xcd_run = 8;
   o->pack_tails = 1;
+  o->split_tails = 1;
   return NR_OK;
 }
 
@@ -596,7 +601,8 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
   nr_plan_options o;
   nr_plan_options_default(&o);
   if (opts) o = *opts;
-  if (o.xcd_run < 1 || o.xcd_run > 64 || (o.pack_tails != 0 && o.pack_tails != 1))
+  if (o.xcd_run < 1 || o.xcd_run > 64 || (o.pack_tails != 0 && o.pack_tails != 1) ||
+      (o.split_tails != 0 && o.split_tails != 1))
     return NR_EINVAL;
   bool bucket_store[kNumBuckets];
   for (int k = 0; k < kNumBuckets; ++k) {
@@ -642,6 +648,7 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
     int32_t item, p0;
     int64_t rec;
     double cost;
+    int32_t split = 0;  // split tail units: points | node groups << 16
   };
   struct Tail {
     int32_t item, p0, count;
@@ -649,6 +656,7 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
   };
   // one list per bucket, then the deep list (kDeepBucket)
   std::vector<std::vector<Wu>> fwd_units(kNumBuckets + 1), grad_units(kNumBuckets + 1);
+  std::vector<std::vector<Wu>> split_units(kNumBuckets);
   int scan_ch = 0;
   std::map<std::pair<int, int>, std::vector<Tail>> tails;  // (depth, nodes)
   std::vector<int64_t> ll_first(nI), ll_offs, gr_first(nI), gr_offs;
@@ -694,8 +702,17 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
       rec_gr += rsz;
     }
     if (ntail > 0) {
-      // the tail's lanes sum into one record of the item
-      tails[{N, K}].push_back({b, nfull * kWuPoints, ntail, rec_gr});
+      // a smeared tail that fills most of a wave with node groups x points
+      // gets a wave of its own (uniform item); else the tail's lanes join a
+      // packed unit and sum into one record of the item
+      const int G = std::min(kWuPoints / ntail, K);
+      if (p->opts.split_tails && K > 1 && ntail >= 4 && G >= 2 && ntail * G >= 48) {
+        Wu u{b, nfull * kWuPoints, rec_gr, (double)ntail * K * (N + 1)};
+        u.split = ntail | (G << 16);
+        split_units[bk].push_back(u);
+      } else {
+        tails[{N, K}].push_back({b, nfull * kWuPoints, ntail, rec_gr});
+      }
       gr_offs.push_back(rec_gr);
       rec_gr += rsz;
     }
@@ -738,33 +755,38 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
   }
 
   // full-unit launches: one per non-empty bucket, deepest first, LPT order
-  auto make_full = [&](std::vector<std::vector<Wu>>& units, std::vector<Launch>& out_list) {
-    for (int bk = kNumBuckets; bk >= 0; --bk) {
+  auto make_full = [&](std::vector<std::vector<Wu>>& units, std::vector<Launch>& out_list,
+                       bool split) {
+    for (int bk = (int)units.size() - 1; bk >= 0; --bk) {
       auto& v = units[bk];
       if (v.empty() || e != hipSuccess) continue;
       std::stable_sort(v.begin(), v.end(), [](const Wu& x, const Wu& y) { return x.cost > y.cost; });
-      std::vector<int32_t> it(v.size()), p0(v.size());
+      std::vector<int32_t> it(v.size()), p0(v.size()), sc(v.size());
       std::vector<int64_t> rc(v.size());
       for (size_t k = 0; k < v.size(); ++k) {
         const size_t src = xcd_order(k, v.size(), (size_t)p->opts.xcd_run);
         it[k] = v[src].item;
         p0[k] = v[src].p0;
         rc[k] = v[src].rec;
+        sc[k] = v[src].split;
       }
       Launch L;
       L.bucket = bk;
       L.store = bk < kNumBuckets && p->bucket_store[bk];
       L.scan_ch = bk == kDeepBucket ? scan_ch : 0;
+      L.split = split;
       L.n_wu = (int)v.size();
       e = upload(&L.item, it);
       keep(L.item);
       if (e == hipSuccess) { e = upload(&L.p0, p0); keep(L.p0); }
       if (e == hipSuccess) { e = upload(&L.rec, rc); keep(L.rec); }
+      if (e == hipSuccess && split) { e = upload(&L.split_code, sc); keep(L.split_code); }
       out_list.push_back(L);
     }
   };
-  make_full(fwd_units, p->launches_fwd);
-  make_full(grad_units, p->launches_grad);
+  make_full(fwd_units, p->launches_fwd, false);
+  make_full(grad_units, p->launches_grad, false);
+  make_full(split_units, p->launches_grad, true);
   if (e == hipSuccess && scan_ch > 0) e = prepare_grad_scan(scan_ch);
   if (e == hipSuccess) e = prepare_reduce(p->max_rows);
 

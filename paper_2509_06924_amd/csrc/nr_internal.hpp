@@ -57,6 +57,8 @@ inline int bucket_of(int N) {
 struct KernelArgs {
   // work list of one launch (launch order)
   const int32_t* wu_item;
+  // split tail units: points | node groups << 16 per unit
+  const int32_t* wu_split;
   const int32_t* wu_p0;
   const int64_t* wu_rec;
   // tail work units: per-lane item, point and record (64 per unit)
@@ -119,10 +121,14 @@ hipError_t launch_forward(int precision, int op, const KernelArgs& a, int n_wu, 
 // to the precision's store limit), and the recompute form that also
 // accumulates the derivative with respect to the relative resolution.
 enum GradForm { kFormRecompute = 0, kFormStore = 1, kFormRecomputeRes = 2 };
-hipError_t launch_grad(int precision, int bucket, int form, bool tail, const KernelArgs& a,
+// mode: kModeFull (64 points of one item), kModeTail (packed partial
+// groups of several items), kModeSplit (one item's partial group, lanes over
+// node groups x points)
+enum WuMode { kModeFull = 0, kModeTail = 1, kModeSplit = 2 };
+hipError_t launch_grad(int precision, int bucket, int form, int mode, const KernelArgs& a,
                        int n_wu, hipStream_t st);
 hipError_t launch_forward_f32(int op, const KernelArgs& a, int n_wu, hipStream_t st);
-hipError_t launch_grad_f32(int bucket, int form, bool tail, const KernelArgs& a, int n_wu,
+hipError_t launch_grad_f32(int bucket, int form, int mode, const KernelArgs& a, int n_wu,
                            hipStream_t st);
 // Deep buckets (index >= kFirstDeepBucket): one object per (precision,
 // bucket), built from nr_kernels_bucket.hip, each exporting
@@ -133,9 +139,9 @@ hipError_t launch_grad_f32(int bucket, int form, bool tail, const KernelArgs& a,
 struct F64;
 struct F32;
 #define NR_DECLARE_DEEP(LM)                                                                  \
-  hipError_t NR_DEEP_LAUNCHER(F64, LM)(int form, bool tail, const KernelArgs& a, int n_wu,  \
+  hipError_t NR_DEEP_LAUNCHER(F64, LM)(int form, int mode, const KernelArgs& a, int n_wu,  \
                                        hipStream_t st);                                      \
-  hipError_t NR_DEEP_LAUNCHER(F32, LM)(int form, bool tail, const KernelArgs& a, int n_wu,  \
+  hipError_t NR_DEEP_LAUNCHER(F32, LM)(int form, int mode, const KernelArgs& a, int n_wu,  \
                                        hipStream_t st);
 NR_BUCKETS_DEEP(NR_DECLARE_DEEP)
 #undef NR_DECLARE_DEEP

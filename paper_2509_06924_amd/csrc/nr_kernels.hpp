@@ -306,6 +306,35 @@ __device__ __forceinline__ WuInfo tail_setup(const KernelArgs& a, int w, int lan
   return u;
 }
 
+// Split tail units hold the last partial group of points (npts < 64) of one
+// smeared item: lane l = g npts + p evaluates point p0 + p on the smearing
+// nodes k = g, g + G, g + 2G, ... (G node groups, G npts <= 64 lanes busy).
+// The item is wave-uniform, so its layer records are scalar loads as in a
+// full unit.  Idle lanes repeat point p0 + (l mod npts) and evaluate no node.
+struct SplitInfo {
+  int g, G, npts;
+};
+__device__ __forceinline__ WuInfo split_setup(const KernelArgs& a, int w, int lane,
+                                              SplitInfo& sp) {
+  const int32_t code = a.wu_split[w];
+  sp.npts = code & 0xffff;
+  sp.G = code >> 16;
+  sp.g = lane / sp.npts;
+  WuInfo u;
+  u.item = a.wu_item[w];
+  const int p0 = a.wu_p0[w];
+  u.ds = a.dataset_of_item[u.item];
+  u.qoff = a.q_off[u.ds];
+  u.nq = (int)(a.q_off[u.ds + 1] - u.qoff);
+  u.roff = a.row_off[u.item];
+  u.N = (int)(a.row_off[u.item + 1] - u.roff) - 2;
+  u.i = p0 + lane % sp.npts;
+  u.active = sp.g < sp.G;
+  u.Q = a.q[u.qoff + u.i];
+  resolution_setup(a, u, u.qoff + u.i);
+  return u;
+}
+
 template <class P>
 __device__ __forceinline__ Layers<P> item_layers(const KernelArgs& a, int64_t roff, int N, int k) {
   Layers<P> L;
@@ -778,9 +807,10 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
 //   [3 + 3NR + m]  sum Re(conj(ubar) kz_{m-1} kz_m)   (sigma_m factor applied later)
 //   [3 + 4NR]      d/d(dQ/Q) (relative resolution)
 // ---------------------------------------------------------------------------
-template <class P, int LMAX, bool STORE, bool TAIL, bool RES>
+template <class P, int LMAX, bool STORE, bool TAIL, bool RES, bool SPLIT = false>
 __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(KernelArgs a) {
   static_assert(!(STORE && RES), "the resolution derivative has the recompute form only");
+  static_assert(!(TAIL && SPLIT), "a unit is packed or split, not both");
   using Re = typename P::real;
   __shared__ Shared s;
   using Tape = typename std::conditional<STORE, GradTape<Re, LMAX>, char>::type;
@@ -790,7 +820,9 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(K
   __shared__ Ef efc;
   const int lane = threadIdx.x;
   const int w = blockIdx.x;
-  const WuInfo u = TAIL ? tail_setup(a, w, lane) : wu_setup(a, w, lane);
+  SplitInfo sp{0, 1, 64};
+  const WuInfo u = TAIL ? tail_setup(a, w, lane)
+                        : SPLIT ? split_setup(a, w, lane, sp) : wu_setup(a, w, lane);
   stage_shared(s, lane, a.rule);
   const int N = u.N;
   const int K = u.smeared ? kSmearNodes : 1;
@@ -809,7 +841,10 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(K
   bool edge = false;
   // dq_k/d(dQ/Q) = Q t_k / (2 sqrt(2 ln 2)) for a relative width
   const double dq_dres = (u.smeared && !u.pointwise) ? u.Q / kFwhmPerSigma : 0.0;
-  for (int k = 0; k < K; ++k) {
+  // a split unit's lane takes every G-th node from its group's first
+  const int k0 = SPLIT ? (u.active ? sp.g : K) : 0;
+  const int kstep = SPLIT ? sp.G : 1;
+  for (int k = k0; k < K; k += kstep) {
     const double tk = ld(s.t[k]);
     const double q = (K == 1) ? u.Q : smear_at(u.Q, u.sig, tk);
     badq |= !(q > 0.0);
@@ -835,6 +870,19 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(K
       if (m == N + 1) acc.Hw[m] = back;
   }
 
+  if constexpr (SPLIT) {
+    // the point's smeared R and its q test over its node groups' lanes
+    double tot = 0.0;
+    int bq = 0;
+    for (int gg = 0; gg < sp.G; ++gg) {
+      const int src = gg * sp.npts + lane % sp.npts;
+      tot += __shfl(Rsm, src, 64);
+      bq |= __shfl(badq ? 1 : 0, src, 64);
+    }
+    Rsm = tot;
+    badq = bq != 0;
+  }
+
   // ---- instrument, likelihood, seeds ----
   double ll = 0.0, gsc = 0.0, gbk = 0.0, fac = 0.0;
   uint32_t bits = 0;
@@ -857,6 +905,12 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(K
     gbk = ghat;
     fac = ghat * sc;
     if (edge) bits |= kItemEdgeSingular;
+    if (SPLIT && sp.g != 0) {
+      // the point's value terms once, from its first node group's lane
+      ll = 0.0;
+      gsc = 0.0;
+      gbk = 0.0;
+    }
   }
   flag(a.item_status, u.item, bits);
 
@@ -961,8 +1015,11 @@ hipError_t launch_forward_p(int op, const KernelArgs& a, int n_wu, hipStream_t s
 // Launch of one gradient bucket; BUCKETS is the list macro of the buckets
 // this translation unit compiles.
 #define NR_LAUNCH(LM, S, RES)                                                                 \
-  if (tail)                                                                                   \
+  if (mode == kModeTail)                                                                      \
     hipLaunchKernelGGL((k_loglik_grad<P, LM, S, true, RES>), dim3(n_wu), dim3(64), 0, st, a);  \
+  else if (mode == kModeSplit)                                                                \
+    hipLaunchKernelGGL((k_loglik_grad<P, LM, S, false, RES, true>), dim3(n_wu), dim3(64), 0,  \
+                       st, a);                                                                \
   else                                                                                        \
     hipLaunchKernelGGL((k_loglik_grad<P, LM, S, false, RES>), dim3(n_wu), dim3(64), 0, st, a);
 // the kernel form (GradForm) of bucket LM
@@ -984,7 +1041,7 @@ hipError_t launch_forward_p(int op, const KernelArgs& a, int n_wu, hipStream_t s
     return hipGetLastError();
 #define NR_DEFINE_GRAD_LAUNCHER(NAME, BUCKETS)                                                \
   template <class P>                                                                          \
-  hipError_t NAME(int bucket, int form, bool tail, const KernelArgs& a, int n_wu,            \
+  hipError_t NAME(int bucket, int form, int mode, const KernelArgs& a, int n_wu,            \
                   hipStream_t st) {                                                           \
     if (n_wu <= 0) return hipSuccess;                                                         \
     switch (kBucketLmax[bucket]) {                                                            \

@@ -10,7 +10,7 @@
 
 namespace nr {
 
-hipError_t NR_DEEP_LAUNCHER(NR_PREC, NR_BUCKET_LMAX)(int form, bool tail, const KernelArgs& a,
+hipError_t NR_DEEP_LAUNCHER(NR_PREC, NR_BUCKET_LMAX)(int form, int mode, const KernelArgs& a,
                                                      int n_wu, hipStream_t st) {
   using P = NR_PREC;
   constexpr int LM = NR_BUCKET_LMAX;

@@ -10,9 +10,9 @@ hipError_t launch_forward_f32(int op, const KernelArgs& a, int n_wu, hipStream_t
   return launch_forward_p<F32>(op, a, n_wu, st);
 }
 
-hipError_t launch_grad_f32(int bucket, int form, bool tail, const KernelArgs& a, int n_wu,
+hipError_t launch_grad_f32(int bucket, int form, int mode, const KernelArgs& a, int n_wu,
                            hipStream_t st) {
-  return launch_grad_shallow<F32>(bucket, form, tail, a, n_wu, st);
+  return launch_grad_shallow<F32>(bucket, form, mode, a, n_wu, st);
 }
 
 }  // namespace nr

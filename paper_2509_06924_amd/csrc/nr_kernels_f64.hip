@@ -123,23 +123,23 @@ hipError_t launch_forward(int precision, int op, const KernelArgs& a, int n_wu, 
                              : launch_forward_p<F64>(op, a, n_wu, st);
 }
 
-hipError_t launch_grad(int precision, int bucket, int form, bool tail, const KernelArgs& a,
+hipError_t launch_grad(int precision, int bucket, int form, int mode, const KernelArgs& a,
                        int n_wu, hipStream_t st) {
   if (bucket == kDeepBucket) return hipErrorInvalidValue;  // launch_grad_scan
   if (bucket >= kFirstDeepBucket) {
     switch (kBucketLmax[bucket]) {
 #define NR_DEEP_CASE(LM)                                                             \
   case LM:                                                                           \
-    return precision == NR_F32 ? NR_DEEP_LAUNCHER(F32, LM)(form, tail, a, n_wu, st) \
-                               : NR_DEEP_LAUNCHER(F64, LM)(form, tail, a, n_wu, st);
+    return precision == NR_F32 ? NR_DEEP_LAUNCHER(F32, LM)(form, mode, a, n_wu, st) \
+                               : NR_DEEP_LAUNCHER(F64, LM)(form, mode, a, n_wu, st);
       NR_BUCKETS_DEEP(NR_DEEP_CASE)
 #undef NR_DEEP_CASE
       default:
         return hipErrorInvalidValue;
     }
   }
-  return precision == NR_F32 ? launch_grad_f32(bucket, form, tail, a, n_wu, st)
-                             : launch_grad_shallow<F64>(bucket, form, tail, a, n_wu, st);
+  return precision == NR_F32 ? launch_grad_f32(bucket, form, mode, a, n_wu, st)
+                             : launch_grad_shallow<F64>(bucket, form, mode, a, n_wu, st);
 }
 
 hipError_t prepare_reduce(int max_rows) {

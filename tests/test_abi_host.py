@@ -149,14 +149,14 @@ def test_plan_options_defaults_and_dict():
     from paper_2509_06924_amd import plan_options
     o = plan_options()
     assert list(o.grad_variant) == [n.NR_VARIANT_AUTO] * n.NR_NUM_BUCKETS
-    assert o.xcd_run == 8 and o.pack_tails == 1
+    assert o.xcd_run == 8 and o.pack_tails == 1 and o.split_tails == 1
     o = plan_options({"grad_variant": {"10": n.NR_VARIANT_RECOMPUTE}, "xcd_run": 4,
                       "pack_tails": 0})
     k10 = [L.nr_bucket_lmax(k) for k in range(n.NR_NUM_BUCKETS)].index(10)
     assert o.grad_variant[k10] == n.NR_VARIANT_RECOMPUTE and o.xcd_run == 4 and o.pack_tails == 0
 
 
-@pytest.mark.parametrize("case", ["xcd_zero", "xcd_big", "pack_two", "variant_unknown",
+@pytest.mark.parametrize("case", ["xcd_zero", "xcd_big", "pack_two", "split_two", "variant_unknown",
                                   "store_too_deep_f64", "store_too_deep_f32"])
 def test_invalid_plan_options_rejected(case):
     n, L = _lib()
@@ -170,6 +170,8 @@ def test_invalid_plan_options_rejected(case):
         o.xcd_run = 65
     elif case == "pack_two":
         o.pack_tails = 2
+    elif case == "split_two":
+        o.split_tails = 2
     elif case == "variant_unknown":
         o.grad_variant[0] = 9
     elif case == "store_too_deep_f64":
