@@ -161,11 +161,12 @@ nr_status nr_plan_create(const nr_batch_desc* desc, nr_plan** plan_out);
  *     the 8 XCDs (1..64; the default 8 keeps an item's units in one L2).
  *   pack_tails: 1 packs the trailing partial point groups of several items
  *     of equal depth into one wave (default); 0 gives each its own wave.
- *   split_tails: 1 (default) gives the trailing partial group of a smeared
- *     item (at least 4 points) a wave of its own whose lanes split the
- *     smearing nodes (lane = node group x point), when that fills at least 48
- *     of the 64 lanes; the item's layer records are then wave-uniform.  Other
- *     tails follow pack_tails.  0: every tail follows pack_tails. */
+ *   split_tails: 1 (default) gives the trailing partial group of an item a
+ *     wave of its own when it fills at least 48 of the 64 lanes: by itself
+ *     (48 points or more), or, for a smeared item of at least 4 points, with
+ *     the lanes split over the smearing nodes (lane = node group x point); the
+ *     item's layer records are then wave-uniform.  Other tails follow
+ *     pack_tails.  0: every tail follows pack_tails. */
 #define NR_NUM_BUCKETS 16
 #define NR_VARIANT_AUTO 0
 #define NR_VARIANT_STORE 1
@@ -180,6 +181,22 @@ typedef struct nr_plan_options {
 /* Fills *opts with the defaults (all NR_VARIANT_AUTO, xcd_run 8,
  * pack_tails 1, split_tails 1).  NR_EINVAL for NULL. */
 nr_status nr_plan_options_default(nr_plan_options* opts);
+
+/* Autotuner: chooses plan options for the batch structure *desc by timing
+ * nr_loglik_grad on the caller's data `v` (device arrays, as for the
+ * evaluation calls) under candidate schedules: per bucket present that has
+ * both forms, the store and the recompute form; xcd_run 1, 4, 8, 16, 32;
+ * pack_tails and split_tails toggled (coordinate search from the defaults,
+ * after a 0.3 s warm-up).  A candidate replaces the current one only when its
+ * median over `reps` timed calls is at least 3 % lower; a final interleaved
+ * comparison keeps the defaults unless the winner holds that margin.  Writes
+ * the options to *best and, if ms is not NULL, the median milliseconds of the
+ * chosen and of the default schedule to ms[0], ms[1].  Allocates and frees
+ * its own plans and device buffers and synchronises `stream` (not for use
+ * inside captured work).  The Python module autotune caches its results per
+ * structure class. */
+nr_status nr_autotune(const nr_batch_desc* desc, const nr_values* v, int32_t reps,
+                      nr_plan_options* best, double* ms, void* stream);
 
 /* Largest layer count L of bucket k (0 <= k < NR_NUM_BUCKETS): items with
  * L <= nr_bucket_lmax(k) and L > nr_bucket_lmax(k-1) are evaluated at depth

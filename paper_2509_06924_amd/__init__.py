@@ -87,6 +87,7 @@ class Plan:
         _n.check(_n.lib().nr_plan_create_ex(ctypes.byref(d), ctypes.byref(self.options),
                                             ctypes.byref(h)))
         self._h = h
+        self.desc = d  # points into the arrays above, which the plan keeps alive
         self.n_items = int(self.dataset_of_item.size)
         self.n_datasets = int(self.dq_over_q.size)
 

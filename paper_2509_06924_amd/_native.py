@@ -29,7 +29,7 @@ EXPORTS = ("nr_version", "nr_status_string", "nr_plan_create", "nr_plan_destroy"
            "nr_store_max_layers", "nr_plan_create_ex", "nr_reflectivity_vjp",
            "nr_loglik_grad_res", "nr_hmc_create", "nr_hmc_destroy", "nr_hmc_init",
            "nr_hmc_transition", "nr_hmc_graph_create", "nr_hmc_adapt", "nr_vi_mvn_create",
-           "nr_vi_mvn_destroy", "nr_vi_mvn_step", "nr_vi_mvn_graph_create")
+           "nr_vi_mvn_destroy", "nr_vi_mvn_step", "nr_vi_mvn_graph_create", "nr_autotune")
 
 
 class BatchDesc(ctypes.Structure):
@@ -207,6 +207,9 @@ def lib():
         L.nr_vi_mvn_graph_create.argtypes = [P, ctypes.POINTER(Values), ctypes.POINTER(MvnParams),
                                              ctypes.c_int32, P, ctypes.c_size_t,
                                              ctypes.POINTER(P)]
+        L.nr_autotune.restype = ctypes.c_int32
+        L.nr_autotune.argtypes = [ctypes.POINTER(BatchDesc), ctypes.POINTER(Values), ctypes.c_int32,
+                                  ctypes.POINTER(PlanOptions), P, P]
         L.nr_tie_sum.restype = ctypes.c_int32
         L.nr_tie_sum.argtypes = [ctypes.c_int64, P, P, P, P, P]
         _lib = L

@@ -6,11 +6,10 @@ recompute form of the gradient kernel; the length of the runs of work units
 given to one XCD; packing of the trailing partial point groups, or a wave of
 their own with the lanes split over smearing-node groups.  Which is
 fastest depends on the batch (depth mix, points per item, number of items)
-and the precision.  `tune` times `nr_loglik_grad` on the caller's own data
-under candidate schedules (coordinate search, CUDA events on the current
-stream, median of a few calls) and returns the fastest options; results are
-cached as JSON keyed by the batch's structure class, so the search runs once
-per class.
+and the precision.  `tune` runs the library's autotuner (nr_autotune: a
+coordinate search timing nr_loglik_grad on the caller's own data with HIP
+events) and returns the fastest options; results are cached as JSON keyed by
+the batch's structure class, so the search runs once per class.
 
     opts = autotune.tune(batch, precision=NR_F64)
     prob = Problem.from_batch(batch, options=opts)
@@ -24,12 +23,8 @@ import os
 import numpy as np
 
 from . import _native as _n
-from . import Plan, Problem, bucket_lmax
+from . import Problem, bucket_lmax
 
-XCD_RUNS = (1, 4, 8, 16, 32)
-MIN_GAIN = 0.03
-WARMUP_S = 0.3
-CONFIRM_ROUNDS = 3
 
 
 def default_cache_path():
@@ -84,26 +79,23 @@ def _save(path, table):
     os.replace(tmp, path)
 
 
-def _time_call(prob, out, reps):
-    import torch
-    stream = torch.cuda.current_stream()
-    prob.loglik_grad(out=out, stream=stream)
-    ts = []
-    for _ in range(reps):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        prob.loglik_grad(out=out, stream=stream)
-        b.record(stream)
-        b.synchronize()
-        ts.append(a.elapsed_time(b))
-    return float(np.median(ts))
+def options_to_dict(o):
+    """nr_plan_options as the dict Plan / Problem.from_batch take."""
+    lm = bucket_lmax()
+    gv = {str(lm[k]): int(o.grad_variant[k]) for k in range(_n.NR_NUM_BUCKETS)
+          if o.grad_variant[k] != _n.NR_VARIANT_AUTO}
+    return {"grad_variant": gv, "xcd_run": int(o.xcd_run), "pack_tails": int(o.pack_tails),
+            "split_tails": int(o.split_tails)}
 
 
 def tune(batch, precision=_n.NR_F64, device="cuda", cache=None, reps=7, verbose=False,
          use_cache=True):
     """Fastest plan options for `batch` (an inputs.Batch or anything with the
-    same fields), as a dict for Plan / Problem.from_batch."""
+    same fields), as a dict for Plan / Problem.from_batch.  The search itself
+    is the library's nr_autotune on the batch's data; results are cached per
+    structure class."""
+    import ctypes
+
     import torch
     dev = torch.device(device)
     if dev.type == "cuda" and dev.index is None:
@@ -115,70 +107,19 @@ def tune(batch, precision=_n.NR_F64, device="cuda", cache=None, reps=7, verbose=
     if key in table:
         return table[key]["options"]
 
-    base = Problem.from_batch(batch, device=dev, precision=precision)
-    out = base.loglik_grad()
-    # warm the device up (clocks, caches) for a fixed time before the first
-    # timed schedule
-    import time as _time
-    t_end = _time.perf_counter() + WARMUP_S
-    while _time.perf_counter() < t_end:
-        _time_call(base, out, 1)
-
-    def problem(opts):
-        plan = Plan(batch.q_off, batch.dq_over_q, batch.dataset_of_item, batch.row_off,
-                    precision, opts)
-        return Problem(plan, base.q, base.r_obs, base.r_err, base.layers, base.scale, base.bkg,
-                       dev)
-
-    lm = bucket_lmax()
-    L = np.diff(np.asarray(batch.row_off)) - 2
-    used = sorted(set(int(lm[k]) for k in np.searchsorted(lm, L) if k < len(lm))) if L.size else []
-    smax = int(_n.lib().nr_store_max_layers(precision))
-    best = {"grad_variant": {}, "xcd_run": 8, "pack_tails": 1, "split_tails": 1}
-    best_t = _time_call(problem(best), out, reps)
-    trials = [(dict(best), best_t)]
-
-    def consider(opts):
-        nonlocal best, best_t
-        t = _time_call(problem(opts), out, reps)
-        trials.append((opts, t))
-        if verbose:
-            print(f"autotune {opts}: {t:.3f} ms")
-        # a schedule replaces the current one only when clearly faster, so
-        # ties (within run-to-run noise) keep the library default
-        if t < best_t * (1.0 - MIN_GAIN):
-            best, best_t = opts, t
-
-    # buckets that have both forms: try each explicitly (one of them is the
-    # library default, which a tie keeps)
-    for b in used:
-        if b <= smax:
-            for v in (_n.NR_VARIANT_STORE, _n.NR_VARIANT_RECOMPUTE):
-                gv = dict(best["grad_variant"])
-                gv[str(b)] = v
-                consider({**best, "grad_variant": gv})
-    for run in XCD_RUNS:
-        if run != best["xcd_run"]:
-            consider({**best, "xcd_run": run})
-    consider({**best, "pack_tails": 1 - best["pack_tails"]})
-    consider({**best, "split_tails": 1 - best["split_tails"]})
-
-    # confirm against the default, interleaved so that drift cancels
-    if best != trials[0][0]:
-        p_def, p_best = problem(trials[0][0]), problem(best)
-        td, tb = [], []
-        for _ in range(CONFIRM_ROUNDS):
-            td.append(_time_call(p_def, out, reps))
-            tb.append(_time_call(p_best, out, reps))
-        if np.median(tb) >= np.median(td) * (1.0 - MIN_GAIN):
-            best, best_t = trials[0][0], float(np.median(td))
-        else:
-            best_t = float(np.median(tb))
-    record = {"options": best, "ms": best_t, "default_ms": trials[0][1],
-              "trials": len(trials)}
+    prob = Problem.from_batch(batch, device=dev, precision=precision)
+    plan = prob.plan
+    o = _n.PlanOptions()
+    ms = (ctypes.c_double * 2)()
+    stream = torch.cuda.current_stream(dev)
+    _n.check(_n.lib().nr_autotune(ctypes.byref(plan.desc), ctypes.byref(prob.values()), int(reps),
+                                  ctypes.byref(o), ctypes.cast(ms, ctypes.c_void_p),
+                                  ctypes.c_void_p(stream.cuda_stream)))
+    best = options_to_dict(o)
+    record = {"options": best, "ms": float(ms[0]), "default_ms": float(ms[1])}
     if use_cache:
         table[key] = record
         _save(path, table)
     if verbose:
-        print(f"autotune best {best}: {best_t:.3f} ms (default {trials[0][1]:.3f} ms)")
+        print(f"autotune best {best}: {ms[0]:.3f} ms (default {ms[1]:.3f} ms)")
     return best

@@ -15,7 +15,7 @@ LIB = os.path.join(PKG, "libnr.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
 SOURCES = ["nr_api.hip", "nr_kernels_f64.hip", "nr_kernels_f32.hip", "nr_integrators.hip",
-           "nr_hmc.hip", "nr_vi_mvn.hip", "nr_kernels_scan.hip"]
+           "nr_hmc.hip", "nr_vi_mvn.hip", "nr_kernels_scan.hip", "nr_autotune.hip"]
 # compiled once per (precision, deep bucket); the bucket list is read from
 # the NR_BUCKETS_DEEP macro so it cannot drift from the C++ side
 BUCKET_SOURCE = "nr_kernels_bucket.hip"

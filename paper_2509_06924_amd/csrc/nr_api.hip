@@ -706,7 +706,10 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
       // gets a wave of its own (uniform item); else the tail's lanes join a
       // packed unit and sum into one record of the item
       const int G = std::min(kWuPoints / ntail, K);
-      if (p->opts.split_tails && K > 1 && ntail >= 4 && G >= 2 && ntail * G >= 48) {
+      if (p->opts.split_tails && ntail >= 48) {
+        // most of a wave: a full unit with idle lanes (uniform item)
+        grad_units[bk].push_back({b, nfull * kWuPoints, rec_gr, (double)ntail * K * (N + 1)});
+      } else if (p->opts.split_tails && K > 1 && ntail >= 4 && G >= 2 && ntail * G >= 48) {
         Wu u{b, nfull * kWuPoints, rec_gr, (double)ntail * K * (N + 1)};
         u.split = ntail | (G << 16);
         split_units[bk].push_back(u);
