@@ -161,12 +161,16 @@ nr_status nr_plan_create(const nr_batch_desc* desc, nr_plan** plan_out);
  *     the 8 XCDs (1..64; the default 8 keeps an item's units in one L2).
  *   pack_tails: 1 packs the trailing partial point groups of several items
  *     of equal depth into one wave (default); 0 gives each its own wave.
- *   split_tails: 1 (default) gives the trailing partial group of an item a
- *     wave of its own when it fills at least 48 of the 64 lanes: by itself
- *     (48 points or more), or, for a smeared item of at least 4 points, with
- *     the lanes split over the smearing nodes (lane = node group x point); the
- *     item's layer records are then wave-uniform.  Other tails follow
- *     pack_tails.  0: every tail follows pack_tails. */
+ *   split_tails (bits): the trailing partial group of an item of at most 10
+ *     layers gets a wave of its own when it fills at least 48 of the 64
+ *     lanes, which keeps the item's layer records wave-uniform:
+ *       NR_TAILS_LONE   by itself (48 points or more);
+ *       NR_TAILS_SPLIT  for a smeared item, with the lanes split over 2 to 4
+ *                       groups of smearing nodes (lane = node group x point;
+ *                       12 to 32 points).
+ *     Other tails follow pack_tails.  Default: both bits. */
+#define NR_TAILS_LONE 1
+#define NR_TAILS_SPLIT 2
 #define NR_NUM_BUCKETS 16
 #define NR_VARIANT_AUTO 0
 #define NR_VARIANT_STORE 1
@@ -179,7 +183,8 @@ typedef struct nr_plan_options {
 } nr_plan_options;
 
 /* Fills *opts with the defaults (all NR_VARIANT_AUTO, xcd_run 8,
- * pack_tails 1, split_tails 1).  NR_EINVAL for NULL. */
+ * pack_tails 1, split_tails NR_TAILS_LONE | NR_TAILS_SPLIT).  NR_EINVAL for
+ * NULL. */
 nr_status nr_plan_options_default(nr_plan_options* opts);
 
 /* Autotuner: chooses plan options for the batch structure *desc by timing

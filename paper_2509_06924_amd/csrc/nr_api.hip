@@ -120,6 +120,8 @@ struct RecordLists {
 // the chunks keep the longest-first order.  The last partial chunk maps to
 // itself.
 constexpr int kXcds = 8;
+// deepest bucket whose partial point groups may get a wave of their own
+constexpr int kSplitTailMaxLayers = 10;
 size_t xcd_order(size_t b, size_t n, size_t run) {
   const size_t chunk = kXcds * run;
   const size_t c0 = (b / chunk) * chunk;
@@ -578,7 +580,7 @@ nr_status nr_plan_options_default(nr_plan_options* o) {
   for (int k = 0; k < NR_NUM_BUCKETS; ++k) o->grad_variant[k] = NR_VARIANT_AUTO;
   o->xcd_run = 8;
   o->pack_tails = 1;
-  o->split_tails = 1;
+  o->split_tails = NR_TAILS_LONE | NR_TAILS_SPLIT;
   return NR_OK;
 }
 
@@ -602,7 +604,7 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
   nr_plan_options_default(&o);
   if (opts) o = *opts;
   if (o.xcd_run < 1 || o.xcd_run > 64 || (o.pack_tails != 0 && o.pack_tails != 1) ||
-      (o.split_tails != 0 && o.split_tails != 1))
+      (o.split_tails & ~(NR_TAILS_LONE | NR_TAILS_SPLIT)))
     return NR_EINVAL;
   bool bucket_store[kNumBuckets];
   for (int k = 0; k < kNumBuckets; ++k) {
@@ -706,10 +708,19 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
       // gets a wave of its own (uniform item); else the tail's lanes join a
       // packed unit and sum into one record of the item
       const int G = std::min(kWuPoints / ntail, K);
-      if (p->opts.split_tails && ntail >= 48) {
+      // measured on MI355X: a wave of its own pays off up to 10 layers (the
+      // 4096-draw batch: 3 % faster); deeper kernels, at one wave per SIMD,
+      // lose more to the idle lanes and the split kernel's registers than
+      // they gain from scalar record loads (16384-item ragged batch: 8 %
+      // slower), so their tails stay packed
+      const bool own_wave = kBucketLmax[bk] <= kSplitTailMaxLayers;
+      if (own_wave && (p->opts.split_tails & NR_TAILS_LONE) && ntail >= 48) {
         // most of a wave: a full unit with idle lanes (uniform item)
         grad_units[bk].push_back({b, nfull * kWuPoints, rec_gr, (double)ntail * K * (N + 1)});
-      } else if (p->opts.split_tails && K > 1 && ntail >= 4 && G >= 2 && ntail * G >= 48) {
+      } else if (own_wave && (p->opts.split_tails & NR_TAILS_SPLIT) && K > 1 && G >= 2 &&
+                 G <= 4 && ntail * G >= 48) {
+        // at least four nodes per lane, so that the wave's epilogue (one
+        // reduction of every record field) stays small beside its work
         Wu u{b, nfull * kWuPoints, rec_gr, (double)ntail * K * (N + 1)};
         u.split = ntail | (G << 16);
         split_units[bk].push_back(u);

@@ -50,7 +50,8 @@ def _check_against_oracle(nr, orc, batch, options):
     {"xcd_run": 1},
     {"xcd_run": 3, "pack_tails": 0},
     {"split_tails": 0},
-    {"split_tails": 1, "pack_tails": 0,
+    {"split_tails": 1},
+    {"split_tails": 2, "pack_tails": 0,
      "grad_variant": {str(k): 2 for k in (1, 2, 4, 6, 8, 10)}},
 ])
 def test_schedules_match_oracle(nr, orc, options):
