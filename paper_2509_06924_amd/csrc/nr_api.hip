@@ -768,6 +768,79 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
     keep(p->d_rule);
   }
 
+  std::vector<Launch> tail_launches;  // after the full units
+  // tail launches: per (depth, nodes) group, largest tails first, first fit
+  // into 64-lane units; then one launch per bucket over all its groups (the
+  // units holding a single item join the full units below)
+  {
+    std::vector<std::vector<int32_t>> b_item(kNumBuckets), b_litem(kNumBuckets), b_lpt(kNumBuckets);
+    std::vector<std::vector<int64_t>> b_lrec(kNumBuckets);
+    for (auto& kv : tails) {
+      const int bk = bucket_of(kv.first.first);
+      auto& v = kv.second;
+      std::stable_sort(v.begin(), v.end(),
+                       [](const Tail& x, const Tail& y) { return x.count > y.count; });
+      std::vector<int> fill;                   // lanes used per unit of this group
+      std::vector<std::vector<size_t>> units;  // the tails of each unit
+      for (size_t t = 0; t < v.size(); ++t) {
+        size_t u = p->opts.pack_tails ? 0 : fill.size();
+        while (u < fill.size() && fill[u] + v[t].count > kWuPoints) ++u;
+        if (u == fill.size()) {
+          fill.push_back(0);
+          units.emplace_back();
+        }
+        units[u].push_back(t);
+        fill[u] += v[t].count;
+      }
+      for (const auto& un : units) {
+        if (un.size() == 1) {
+          // a unit of one item is a full unit with idle lanes (its layer
+          // records stay scalar loads)
+          const Tail& t = v[un[0]];
+          grad_units[bk].push_back(
+              {t.item, t.p0, t.rec0, (double)t.count * kv.first.second * (kv.first.first + 1)});
+          continue;
+        }
+        const size_t base = b_item[bk].size() * kWuPoints;
+        b_item[bk].push_back(v[un[0]].item);
+        b_litem[bk].insert(b_litem[bk].end(), kWuPoints, -1);
+        b_lpt[bk].insert(b_lpt[bk].end(), kWuPoints, 0);
+        b_lrec[bk].insert(b_lrec[bk].end(), kWuPoints, -1);
+        int f = 0;
+        for (size_t ti : un) {
+          const Tail& t = v[ti];
+          for (int l = 0; l < t.count; ++l) {
+            b_litem[bk][base + f + l] = t.item;
+            b_lpt[bk][base + f + l] = t.p0 + l;
+            b_lrec[bk][base + f + l] = t.rec0;
+          }
+          f += t.count;
+        }
+      }
+    }
+    for (int bk = kNumBuckets - 1; bk >= 0; --bk) {
+      if (b_item[bk].empty() || e != hipSuccess) continue;
+      // idle lanes repeat lane 0 of their unit (a valid point, result unused)
+      for (size_t u = 0; u < b_item[bk].size(); ++u)
+        for (int l = 0; l < kWuPoints; ++l)
+          if (b_litem[bk][u * kWuPoints + l] < 0) {
+            b_litem[bk][u * kWuPoints + l] = b_litem[bk][u * kWuPoints];
+            b_lpt[bk][u * kWuPoints + l] = b_lpt[bk][u * kWuPoints];
+          }
+      Launch L;
+      L.bucket = bk;
+      L.store = p->bucket_store[bk];
+      L.tail = true;
+      L.n_wu = (int)b_item[bk].size();
+      e = upload(&L.item, b_item[bk]);
+      keep(L.item);
+      if (e == hipSuccess) { e = upload(&L.lane_item, b_litem[bk]); keep(L.lane_item); }
+      if (e == hipSuccess) { e = upload(&L.lane_pt, b_lpt[bk]); keep(L.lane_pt); }
+      if (e == hipSuccess) { e = upload(&L.lane_rec, b_lrec[bk]); keep(L.lane_rec); }
+      tail_launches.push_back(L);
+    }
+  }
+
   // full-unit launches: one per non-empty bucket, deepest first, LPT order
   auto make_full = [&](std::vector<std::vector<Wu>>& units, std::vector<Launch>& out_list,
                        bool split) {
@@ -801,63 +874,10 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
   make_full(fwd_units, p->launches_fwd, false);
   make_full(grad_units, p->launches_grad, false);
   make_full(split_units, p->launches_grad, true);
+  p->launches_grad.insert(p->launches_grad.end(), tail_launches.begin(), tail_launches.end());
   if (e == hipSuccess && scan_ch > 0) e = prepare_grad_scan(scan_ch);
   if (e == hipSuccess) e = prepare_reduce(p->max_rows);
 
-  // tail launches: per (depth, nodes) group, largest tails first, first fit
-  // into 64-lane units; then one launch per bucket over all its groups
-  {
-    std::vector<std::vector<int32_t>> b_item(kNumBuckets), b_litem(kNumBuckets), b_lpt(kNumBuckets);
-    std::vector<std::vector<int64_t>> b_lrec(kNumBuckets);
-    for (auto& kv : tails) {
-      const int bk = bucket_of(kv.first.first);
-      auto& v = kv.second;
-      std::stable_sort(v.begin(), v.end(),
-                       [](const Tail& x, const Tail& y) { return x.count > y.count; });
-      std::vector<int> fill;  // lanes used per unit of this group
-      std::vector<size_t> unit_base;
-      for (const Tail& t : v) {
-        size_t u = p->opts.pack_tails ? 0 : fill.size();
-        while (u < fill.size() && fill[u] + t.count > kWuPoints) ++u;
-        if (u == fill.size()) {
-          fill.push_back(0);
-          unit_base.push_back(b_item[bk].size());
-          b_item[bk].push_back(t.item);
-          b_litem[bk].insert(b_litem[bk].end(), kWuPoints, -1);
-          b_lpt[bk].insert(b_lpt[bk].end(), kWuPoints, 0);
-          b_lrec[bk].insert(b_lrec[bk].end(), kWuPoints, -1);
-        }
-        const size_t base = unit_base[u] * kWuPoints;
-        for (int l = 0; l < t.count; ++l) {
-          b_litem[bk][base + fill[u] + l] = t.item;
-          b_lpt[bk][base + fill[u] + l] = t.p0 + l;
-          b_lrec[bk][base + fill[u] + l] = t.rec0;
-        }
-        fill[u] += t.count;
-      }
-    }
-    for (int bk = kNumBuckets - 1; bk >= 0; --bk) {
-      if (b_item[bk].empty() || e != hipSuccess) continue;
-      // idle lanes repeat lane 0 of their unit (a valid point, result unused)
-      for (size_t u = 0; u < b_item[bk].size(); ++u)
-        for (int l = 0; l < kWuPoints; ++l)
-          if (b_litem[bk][u * kWuPoints + l] < 0) {
-            b_litem[bk][u * kWuPoints + l] = b_litem[bk][u * kWuPoints];
-            b_lpt[bk][u * kWuPoints + l] = b_lpt[bk][u * kWuPoints];
-          }
-      Launch L;
-      L.bucket = bk;
-      L.store = p->bucket_store[bk];
-      L.tail = true;
-      L.n_wu = (int)b_item[bk].size();
-      e = upload(&L.item, b_item[bk]);
-      keep(L.item);
-      if (e == hipSuccess) { e = upload(&L.lane_item, b_litem[bk]); keep(L.lane_item); }
-      if (e == hipSuccess) { e = upload(&L.lane_pt, b_lpt[bk]); keep(L.lane_pt); }
-      if (e == hipSuccess) { e = upload(&L.lane_rec, b_lrec[bk]); keep(L.lane_rec); }
-      p->launches_grad.push_back(L);
-    }
-  }
   if (e != hipSuccess) {
     plan_free(p);
     delete p;

@@ -75,3 +75,24 @@ def test_autotune_choice_and_cache(nr, orc, tmp_path):
     assert np.max(np.abs((a[1] - b[1]) * units)) <= 1e-10 * scale
     # and the tuned schedule still matches the oracle on a few items
     _check_against_oracle(nr, orc, batch.subset(np.arange(3)), opts)
+
+
+def test_native_autotune_entry_point(nr):
+    """nr_autotune through the C ABI: valid options that build a plan, and
+    the defaults' and the winner's timings."""
+    import ctypes
+    from paper_2509_06924_amd import _native as n, autotune, inputs
+    batch = inputs.c2_batched(n_items=256, L=4)
+    prob = nr.Problem.from_batch(batch)
+    o = n.PlanOptions()
+    ms = (ctypes.c_double * 2)()
+    import torch
+    st = n.lib().nr_autotune(ctypes.byref(prob.plan.desc), ctypes.byref(prob.values()), 2,
+                             ctypes.byref(o), ctypes.cast(ms, ctypes.c_void_p),
+                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == n.NR_OK
+    assert ms[0] > 0 and ms[1] > 0 and ms[0] <= ms[1] * 1.0001
+    opts = autotune.options_to_dict(o)
+    nr.Problem.from_batch(batch, options=opts).loglik_grad()
+    assert n.lib().nr_autotune(None, ctypes.byref(prob.values()), 2, ctypes.byref(o), None,
+                               None) == n.NR_EINVAL

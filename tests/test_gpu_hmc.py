@@ -211,3 +211,24 @@ def test_invalid_configuration_rejected(nr):
                 n.HmcConfig(5, -1.0, 1, 0.8)):
         assert n.lib().nr_hmc_create(prob.plan.handle, ctypes.byref(cfg),
                                      ctypes.byref(h)) == n.NR_EINVAL
+
+
+def test_fp32_plan_transitions_close_to_fp64(nr):
+    """The driver around an FP32 plan: same draws and decisions as FP64 on a
+    well-conditioned step, positions within the FP32 gradient's error."""
+    batch = _batch(960)
+    steps = np.full(4, 2e-3)
+    kind, a, b, kind_i, a_i, b_i = _transforms(batch)
+    im_r, im_i = _inverse_mass(batch)
+    out = {}
+    for prec in (nr.NR_F64, nr.NR_F32):
+        prob = nr.Problem.from_batch(batch, precision=prec)
+        h = nr.HMC(prob, kind, kind_i, a, b, a_i, b_i, im_r, im_i, step=steps, n_leapfrog=3,
+                   seed=SEED).init(from_theta=True)
+        for _ in range(2):
+            h.transition()
+        out[prec] = (h.n_accept.cpu().numpy(), h.z_rows.cpu().numpy(), h.logL.cpu().numpy())
+        h.close()
+    assert np.array_equal(out[nr.NR_F64][0], out[nr.NR_F32][0])
+    assert np.allclose(out[nr.NR_F32][1], out[nr.NR_F64][1], rtol=1e-3, atol=1e-6)
+    assert np.allclose(out[nr.NR_F32][2], out[nr.NR_F64][2], rtol=1e-4)

@@ -154,3 +154,20 @@ def test_invalid_configuration_rejected(nr):
                 n.MvnConfig(2, 3, 0.05, 1.0, 0.999, 1e-8, 0)):
         assert n.lib().nr_vi_mvn_create(prob.plan.handle, ctypes.byref(cfg),
                                         ctypes.byref(h)) == n.NR_EINVAL
+
+
+def test_fp32_plan_close_to_fp64(nr):
+    """The full-rank step around an FP32 plan: the ELBO and its gradient
+    within the FP32 variant's error of the FP64 ones."""
+    R, S = 2, 4
+    batch, data, nrow, kind, a, b, theta, mu = _setup(R, S, 3, 40, 0.05, 997)
+    out = {}
+    for prec in (nr.NR_F64, nr.NR_F32):
+        prob = nr.Problem.from_batch(batch, precision=prec)
+        vi = nr.MvnVI(prob, R, S, kind, a, b, theta, mu=mu, seed=SEED)
+        vi.step(adam=False)
+        out[prec] = (vi.elbo.cpu().numpy(), vi.grad_mu.cpu().numpy())
+        vi.close()
+    assert np.allclose(out[nr.NR_F32][0], out[nr.NR_F64][0], rtol=1e-5)
+    g64, g32 = out[nr.NR_F64][1], out[nr.NR_F32][1]
+    assert np.max(np.abs(g32 - g64)) <= 1e-2 * np.max(np.abs(g64))
