@@ -67,6 +67,8 @@ struct F64 {
   // recompute variant: keep the state of every second level only (the
   // register tape of the deepest buckets otherwise spills to scratch)
   static constexpr bool checkpoint(int lmax) { return lmax == 12 || lmax == 14 || lmax >= 28; }
+  // one wave per SIMD: the node's scheduling regions span several levels
+  static constexpr bool grouped_regions(int lmax) { return min_waves(lmax, false) == 1; }
 };
 struct F32 {
   using real = float;
@@ -79,6 +81,10 @@ struct F32 {
     return lmax <= 16 ? (lmax + 1 < 16 ? lmax + 1 : 16) : (lmax + 1 < 35 ? lmax + 1 : 35);
   }
   static constexpr bool checkpoint(int lmax) { return lmax >= 32; }
+  // one wave per SIMD, except with the checkpointed tape (measured slower)
+  static constexpr bool grouped_regions(int lmax) {
+    return min_waves(lmax, false) == 1 && !checkpoint(lmax);
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -681,6 +687,15 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
   // re-formed in the adjoint by applying level j + 1 to the state at j + 1
   constexpr int NT = CK ? LMAX / 2 + 1 : LMAX + 1;
   Cx tapeP[NT], tapeQ[NT];
+  // Scheduling regions.  With two waves per SIMD the registers are tight and
+  // the other wave hides latency, so every level is a region of its own.  A
+  // lone wave per SIMD has nothing to hide the latency of its scalar record
+  // loads and LDS table lookups but the independent work of neighbouring
+  // levels (the kz, interface and phase of one level do not depend on the
+  // state), so the forward sweep is one region and the adjoint is cut every
+  // kAdjGroup levels (where the precision policy's grouped_regions says so).
+  constexpr bool kGrouped = P::grouped_regions(LMAX);
+  constexpr int kAdjGroup = kGrouped ? 8 : 1;
   Cx kzn = medium_root(L, kz0sq, LMAX + 1, edge).kz;
   Cx Pv = mk(Re(1), Re(0)), Qv = mk(Re(0), Re(0));
 #pragma unroll
@@ -703,7 +718,8 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
     Qv = (jj >= 1) ? e * t : t;
     Pv = Pn;
     kzn = kzc;
-    __builtin_amdgcn_sched_barrier(0x0100);  // only LDS reads may move across
+    if (!kGrouped || jj == 0)
+      __builtin_amdgcn_sched_barrier(0x0100);  // only LDS reads may move across
   }
   const Cx iP = crecip(Pv);
   const Cx r = Qv * iP;
@@ -768,7 +784,8 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
       step(jj, lv, tapeP[jj], tapeQ[jj], kzc, iac);
       kzc = lv.rn.kz;
       iac = lv.rn.inv_abs2;
-      __builtin_amdgcn_sched_barrier(0x0100);  // only LDS reads may move across
+      if ((jj + 1) % kAdjGroup == 0)
+        __builtin_amdgcn_sched_barrier(0x0100);  // only LDS reads may move across
     }
   } else {
     {
@@ -789,7 +806,8 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
       step(jj + 1, lb, P1, Q1, la.rn.kz, la.rn.inv_abs2);
       kzc = lb.rn.kz;
       iac = lb.rn.inv_abs2;
-      __builtin_amdgcn_sched_barrier(0x0100);  // only LDS reads may move across
+      if ((jj + 1) % kAdjGroup == 0)
+        __builtin_amdgcn_sched_barrier(0x0100);  // only LDS reads may move across
     }
   }
   // Hq += c dR/dq (seeded): dkz0/dq = 1/2 (added at level 0), dw_j/dq = kz0
