@@ -131,6 +131,12 @@ def lib():
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build it with python -m paper_2509_06924_amd.build "
                 "(the HIP library is the only implementation)")
+        # torch ships a HIP runtime of its own under the same soname.  Loading
+        # it first makes this library bind to that runtime: one runtime per
+        # process, so torch's streams and device pointers are valid here (if
+        # this library loaded the system runtime first, torch would then find
+        # no GPU).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.c_void_p
         L.nr_version.restype = ctypes.c_int32

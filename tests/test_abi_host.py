@@ -197,3 +197,21 @@ def test_autotune_structure_key_classes():
     assert k(a) == k(b)
     assert k(a) != k(c) and k(a) != k(a, 1)
     assert k(a) != k(inputs.c2_batched(n_items=1024))
+
+
+def test_binding_shares_torchs_hip_runtime():
+    """Loading the library before torch is touched must still leave one HIP
+    runtime in the process, torch's (a second runtime would make torch's
+    streams invalid in the library and, loaded first, hide the GPU from
+    torch)."""
+    import subprocess
+    import sys
+    code = ("import paper_2509_06924_amd as nr\n"
+            "nr._n.lib()\n"
+            "import torch, os\n"
+            "rt = sorted(set(l.split()[-1] for l in open('/proc/self/maps') if 'amdhip64' in l))\n"
+            "print(len(rt), os.path.dirname(rt[0]) == os.path.dirname(torch.__file__) + '/lib')\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.split() == ["1", "True"], r.stdout
