@@ -67,24 +67,27 @@ struct F64 {
   // recompute variant: keep the state of every second level only (the
   // register tape of the deepest buckets otherwise spills to scratch)
   static constexpr bool checkpoint(int lmax) { return lmax == 12 || lmax == 14 || lmax >= 28; }
-  // one wave per SIMD: the node's scheduling regions span several levels
+  // the node's scheduling regions span several levels: at one wave per SIMD
   static constexpr bool grouped_regions(int lmax) { return min_waves(lmax, false) == 1; }
 };
 struct F32 {
   using real = float;
   static constexpr int kStoreMax = kStoreMaxLayersF32;
   static constexpr int kSlimMax = 0;
-  static constexpr int min_waves(int lmax, bool) { return lmax <= 10 ? 2 : 1; }
-  // 1 KB per level; up to 16 layers the kernel keeps two waves per SIMD, so
-  // its LDS stays within 20 KB
+  // two waves per SIMD up to 20 layers, except 16, where one wave with
+  // multi-level scheduling regions measured 3 % faster (the FP64 gradient
+  // accumulators dominate the registers; 18 and 20 layers fit with the
+  // checkpointed tape and ran 23 % faster than at one wave)
+  static constexpr int min_waves(int lmax, bool) { return (lmax <= 20 && lmax != 16) ? 2 : 1; }
+  // 1 KB per level; up to 20 layers the LDS of a kernel that may share the
+  // SIMD with a second wave stays within 20 KB
   static constexpr int ef_levels(int lmax) {
-    return lmax <= 16 ? (lmax + 1 < 16 ? lmax + 1 : 16) : (lmax + 1 < 35 ? lmax + 1 : 35);
+    return lmax <= 20 ? (lmax + 1 < 16 ? lmax + 1 : 16) : (lmax + 1 < 35 ? lmax + 1 : 35);
   }
-  static constexpr bool checkpoint(int lmax) { return lmax >= 32; }
-  // one wave per SIMD, except with the checkpointed tape (measured slower)
-  static constexpr bool grouped_regions(int lmax) {
-    return min_waves(lmax, false) == 1 && !checkpoint(lmax);
-  }
+  static constexpr bool checkpoint(int lmax) { return lmax == 18 || lmax == 20 || lmax >= 32; }
+  // from 12 layers, at one or two waves per SIMD (12 layers 5 % faster, 14-28
+  // equal or faster); not at 32-40 layers (3-5 % slower)
+  static constexpr bool grouped_regions(int lmax) { return lmax >= 12 && lmax < 32; }
 };
 
 // ---------------------------------------------------------------------------
@@ -687,13 +690,14 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
   // re-formed in the adjoint by applying level j + 1 to the state at j + 1
   constexpr int NT = CK ? LMAX / 2 + 1 : LMAX + 1;
   Cx tapeP[NT], tapeQ[NT];
-  // Scheduling regions.  With two waves per SIMD the registers are tight and
-  // the other wave hides latency, so every level is a region of its own.  A
-  // lone wave per SIMD has nothing to hide the latency of its scalar record
-  // loads and LDS table lookups but the independent work of neighbouring
-  // levels (the kz, interface and phase of one level do not depend on the
-  // state), so the forward sweep is one region and the adjoint is cut every
-  // kAdjGroup levels (where the precision policy's grouped_regions says so).
+  // Scheduling regions.  By default every level is a region of its own,
+  // which keeps the registers of a two-wave kernel in check.  The latency of
+  // the scalar record loads and LDS table lookups can then only be hidden by
+  // another wave.  Where the precision policy's grouped_regions says so (all
+  // one-wave FP64 kernels, FP32 from 12 layers), the forward sweep is one
+  // region and the adjoint is cut every kAdjGroup levels.  The kz, interface
+  // and phase of one level do not depend on the state, so the scheduler
+  // overlaps neighbouring levels' chains.
   constexpr bool kGrouped = P::grouped_regions(LMAX);
   constexpr int kAdjGroup = kGrouped ? 8 : 1;
   Cx kzn = medium_root(L, kz0sq, LMAX + 1, edge).kz;
