@@ -74,17 +74,19 @@ struct F32 {
   using real = float;
   static constexpr int kStoreMax = kStoreMaxLayersF32;
   static constexpr int kSlimMax = 0;
-  // two waves per SIMD up to 20 layers, except 16, where one wave with
-  // multi-level scheduling regions measured 3 % faster (the FP64 gradient
-  // accumulators dominate the registers; 18 and 20 layers fit with the
-  // checkpointed tape and ran 23 % faster than at one wave)
-  static constexpr int min_waves(int lmax, bool) { return (lmax <= 20 && lmax != 16) ? 2 : 1; }
-  // 1 KB per level; up to 20 layers the LDS of a kernel that may share the
+  // two waves per SIMD up to 28 layers, except 16, where one wave with
+  // multi-level scheduling regions measured 3 % faster.  The FP64 gradient
+  // accumulators dominate the registers; from 18 layers the checkpointed
+  // tape keeps the spill small (none at 18, 204 B per lane at 24, 364 B at
+  // 28), and two waves ran 23, 22 and 4 % faster than one at 20, 24 and 28
+  // layers; at 32-40 layers (516-836 B) they lost 6-27 %.
+  static constexpr int min_waves(int lmax, bool) { return (lmax <= 28 && lmax != 16) ? 2 : 1; }
+  // 1 KB per level; up to 28 layers the LDS of a kernel that may share the
   // SIMD with a second wave stays within 20 KB
   static constexpr int ef_levels(int lmax) {
-    return lmax <= 20 ? (lmax + 1 < 16 ? lmax + 1 : 16) : (lmax + 1 < 35 ? lmax + 1 : 35);
+    return lmax <= 28 ? (lmax + 1 < 16 ? lmax + 1 : 16) : (lmax + 1 < 35 ? lmax + 1 : 35);
   }
-  static constexpr bool checkpoint(int lmax) { return lmax == 18 || lmax == 20 || lmax >= 32; }
+  static constexpr bool checkpoint(int lmax) { return lmax == 18 || lmax == 20 || lmax >= 24; }
   // from 12 layers, at one or two waves per SIMD (12 layers 5 % faster, 14-28
   // equal or faster); not at 32-40 layers (3-5 % slower)
   static constexpr bool grouped_regions(int lmax) { return lmax >= 12 && lmax < 32; }
