@@ -33,8 +33,16 @@ FP64_VALU_PEAK = 78.6e12  # MI355X dense FP64 vector, FLOP/s
 FP32_VALU_PEAK = 157.3e12  # MI355X FP32 vector (counts packed FP32), FLOP/s
 
 # Algorithmic FP64 operations per layer-step of the forward + reverse sweep
-# (operation count of the method; FMA = 2; special functions at fixed costs:
-#  sqrt 10, divide 10, exp 20, sin+cos 40).  Derivation in the design doc.
+# (operation count of the method; FMA = 2, complex multiply 6, complex add 2,
+# abs^2 3; special functions at fixed costs: sqrt 10, divide or reciprocal
+# 10, exp 20, sin+cos 40).  Forward: the complex root of w 36, the Fresnel
+# coefficient 25, the Nevot-Croce factor and r' 76, the phase and its
+# reciprocal 79, the state update 40.  Reverse (the adjoint of the scaled
+# form): re-formed t 8, the cotangents of e, t, r', the states, r and the
+# Nevot-Croce exponent 54, the sigma sum 4, kz terms through the
+# Nevot-Croce exponent 16, through the Fresnel coefficient 36, their
+# combination 4, the phase and thickness terms 24, the chain rule through the
+# root 21.
 FLOP_FWD_PER_LAYER_STEP = 257
 FLOP_ADJ_PER_LAYER_STEP = 167
 FLOP_PER_LAYER_STEP = FLOP_FWD_PER_LAYER_STEP + FLOP_ADJ_PER_LAYER_STEP
