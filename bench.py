@@ -35,7 +35,7 @@ FP32_VALU_PEAK = 157.3e12  # MI355X FP32 vector (counts packed FP32), FLOP/s
 # Algorithmic FP64 operations per layer-step of the forward + reverse sweep
 # (operation count of the method; FMA = 2, complex multiply 6, complex add 2,
 # abs^2 3; special functions at fixed costs: sqrt 10, divide or reciprocal
-# 10, exp 20, sin+cos 40).  Forward: the complex root of w 36, the Fresnel
+# 10, exp 20, sin+cos 40).  Forward: w 1, its complex root 36, the Fresnel
 # coefficient 25, the Nevot-Croce factor and r' 76, the phase and its
 # reciprocal 79, the state update 40.  Reverse (the adjoint of the scaled
 # form): re-formed t 8, the cotangents of e, t, r', the states, r and the
