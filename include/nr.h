@@ -168,7 +168,18 @@ nr_status nr_plan_create(const nr_batch_desc* desc, nr_plan** plan_out);
  *       NR_TAILS_SPLIT  for a smeared item, with the lanes split over 2 to 4
  *                       groups of smearing nodes (lane = node group x point;
  *                       12 to 32 points).
- *     Other tails follow pack_tails.  Default: both bits. */
+ *     Other tails follow pack_tails.  Default: both bits.
+ *   side_stream: 1 (default) runs the gradient's tail and split launches
+ *     that hold at most one round of the device (two waves per SIMD of
+ *     every compute unit) on a second stream that the plan owns (default
+ *     priority, non-blocking), forked from the caller's stream after the
+ *     per-layer constants and joined back before the reduction, so that
+ *     those small launches run beside the full-unit launches instead of
+ *     leaving most of the device idle after them; 0 keeps every launch on
+ *     the caller's stream.  The fork and join are event waits, so
+ *     calls stay ordered on the caller's stream and can be captured into a
+ *     HIP graph (the side stream joins the capture).  Calls on one plan from
+ *     several host threads are serialised around the fork and join. */
 #define NR_TAILS_LONE 1
 #define NR_TAILS_SPLIT 2
 #define NR_NUM_BUCKETS 16
@@ -180,18 +191,19 @@ typedef struct nr_plan_options {
   int32_t xcd_run;
   int32_t pack_tails;
   int32_t split_tails;
+  int32_t side_stream;
 } nr_plan_options;
 
 /* Fills *opts with the defaults (all NR_VARIANT_AUTO, xcd_run 8,
- * pack_tails 1, split_tails NR_TAILS_LONE | NR_TAILS_SPLIT).  NR_EINVAL for
- * NULL. */
+ * pack_tails 1, split_tails NR_TAILS_LONE | NR_TAILS_SPLIT, side_stream 1).
+ * NR_EINVAL for NULL. */
 nr_status nr_plan_options_default(nr_plan_options* opts);
 
 /* Autotuner: chooses plan options for the batch structure *desc by timing
  * nr_loglik_grad on the caller's data `v` (device arrays, as for the
  * evaluation calls) under candidate schedules: per bucket present that has
  * both forms, the store and the recompute form; xcd_run 1, 4, 8, 16, 32;
- * pack_tails and split_tails toggled (coordinate search from the defaults,
+ * pack_tails, split_tails and side_stream toggled (coordinate search from the defaults,
  * after a 0.3 s warm-up).  A candidate replaces the current one only when its
  * median over `reps` timed calls is at least 3 % lower; a final interleaved
  * comparison keeps the defaults unless the winner holds that margin.  Writes

@@ -60,6 +60,8 @@ def plan_options(options=None):
         o.pack_tails = int(options["pack_tails"])
     if "split_tails" in options:
         o.split_tails = int(options["split_tails"])
+    if "side_stream" in options:
+        o.side_stream = int(options["side_stream"])
     return o
 
 
@@ -70,7 +72,7 @@ class Plan:
                  options=None):
         """options: None (defaults) or a dict with any of grad_variant (list of
         NR_NUM_BUCKETS ints or {bucket_lmax: variant}), xcd_run, pack_tails,
-        split_tails."""
+        split_tails, side_stream."""
         self.q_off = np.ascontiguousarray(q_off, np.int64)
         self.dq_over_q = np.ascontiguousarray(dq_over_q, np.float64)
         self.dataset_of_item = np.ascontiguousarray(dataset_of_item, np.int32)

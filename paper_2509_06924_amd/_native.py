@@ -51,6 +51,7 @@ class PlanOptions(ctypes.Structure):
         ("xcd_run", ctypes.c_int32),
         ("pack_tails", ctypes.c_int32),
         ("split_tails", ctypes.c_int32),
+        ("side_stream", ctypes.c_int32),
     ]
 
 

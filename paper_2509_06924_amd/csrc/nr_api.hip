@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -95,6 +96,7 @@ struct Launch {
   bool tail = false;
   bool split = false;  // split tail units (one item's partial group, lanes over node groups)
   int scan_ch = 0;     // deep list: the largest levels-per-lane of its items
+  bool side = false;   // runs on the plan's side stream
   int n_wu = 0;
   int32_t* item = nullptr;      // [n_wu]: the unit's item (first item for tails)
   int32_t* split_code = nullptr;  // [n_wu] split units: points | node groups << 16
@@ -165,6 +167,10 @@ struct nr_plan {
   int max_rows = 2;               // rows of the deepest item
   double node_t[kSmearNodes], node_w[kSmearNodes];
   std::vector<void*> owned;
+  // second stream for the gradient's tail and split launches (side_stream)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  mutable std::mutex side_mu;  // one fork ... join sequence at a time
 };
 
 namespace {
@@ -173,6 +179,11 @@ void plan_free(nr_plan* p) {
   for (void* ptr : p->owned)
     if (ptr) (void)hipFree(ptr);
   p->owned.clear();
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+  if (p->side) (void)hipStreamDestroy(p->side);
+  p->ev_fork = p->ev_join = nullptr;
+  p->side = nullptr;
 }
 
 nr_status validate_desc(const nr_batch_desc* d) {
@@ -266,6 +277,17 @@ nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st, b
     if (e != hipSuccess) return hip_fail(e, "timing event");
   }
   const bool grad = (op == kOpLoglikGrad);
+  // fork: the side stream waits for the constants (and everything before
+  // them on st); join: st waits for the side stream's launches
+  const bool fork = grad && p->side != nullptr;
+  std::unique_lock<std::mutex> lock;
+  if (fork) {
+    lock = std::unique_lock<std::mutex>(p->side_mu);
+    hipError_t e = hipEventRecord(p->ev_fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_fork, 0);
+    if (e != hipSuccess) return hip_fail(e, "side stream fork");
+  }
+  hipError_t launch_err = hipSuccess;
   for (const Launch& L : grad ? p->launches_grad : p->launches_fwd) {
     a.wu_item = L.item;
     a.wu_p0 = L.p0;
@@ -276,15 +298,22 @@ nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st, b
     a.tail_rec = L.lane_rec;
     const int form = res ? kFormRecomputeRes : L.store ? kFormStore : kFormRecompute;
     const int mode = L.tail ? kModeTail : L.split ? kModeSplit : kModeFull;
-    hipError_t e;
+    const hipStream_t ls = (fork && L.side) ? p->side : st;
     if (!grad)
-      e = launch_forward(p->precision, op, a, L.n_wu, st);
+      launch_err = launch_forward(p->precision, op, a, L.n_wu, ls);
     else if (L.bucket == kDeepBucket)
-      e = launch_grad_scan(res, L.scan_ch, a, L.n_wu, st);
+      launch_err = launch_grad_scan(res, L.scan_ch, a, L.n_wu, ls);
     else
-      e = launch_grad(p->precision, L.bucket, form, mode, a, L.n_wu, st);
-    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+      launch_err = launch_grad(p->precision, L.bucket, form, mode, a, L.n_wu, ls);
+    if (launch_err != hipSuccess) break;
   }
+  if (fork) {
+    // joined even after a failed launch, so that a capture stays well formed
+    hipError_t e = hipEventRecord(p->ev_join, p->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_join, 0);
+    if (e != hipSuccess && launch_err == hipSuccess) return hip_fail(e, "side stream join");
+  }
+  if (launch_err != hipSuccess) return hip_fail(launch_err, "kernel launch");
   if (events && p->ev_stop) {
     hipError_t e = hipEventRecord(p->ev_stop, st);
     if (e != hipSuccess) return hip_fail(e, "timing event");
@@ -581,6 +610,7 @@ nr_status nr_plan_options_default(nr_plan_options* o) {
   o->xcd_run = 8;
   o->pack_tails = 1;
   o->split_tails = NR_TAILS_LONE | NR_TAILS_SPLIT;
+  o->side_stream = 1;
   return NR_OK;
 }
 
@@ -604,7 +634,8 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
   nr_plan_options_default(&o);
   if (opts) o = *opts;
   if (o.xcd_run < 1 || o.xcd_run > 64 || (o.pack_tails != 0 && o.pack_tails != 1) ||
-      (o.split_tails & ~(NR_TAILS_LONE | NR_TAILS_SPLIT)))
+      (o.split_tails & ~(NR_TAILS_LONE | NR_TAILS_SPLIT)) ||
+      (o.side_stream != 0 && o.side_stream != 1))
     return NR_EINVAL;
   bool bucket_store[kNumBuckets];
   for (int k = 0; k < kNumBuckets; ++k) {
@@ -873,8 +904,24 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
   };
   make_full(fwd_units, p->launches_fwd, false);
   make_full(grad_units, p->launches_grad, false);
+  const size_t n_main = p->launches_grad.size();
   make_full(split_units, p->launches_grad, true);
   p->launches_grad.insert(p->launches_grad.end(), tail_launches.begin(), tail_launches.end());
+  // Tail and split launches of at most one round of the chip (two waves per
+  // SIMD) leave most of it idle when they run after the full units; on the
+  // side stream they run beside them.  Larger ones gain nothing there and
+  // only interfere (the 4096-draw batch's 4096 split units: 2 % slower).
+  if (e == hipSuccess && p->opts.side_stream && n_main > 0) {
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    const int round = 2 * 4 * std::max(cus, 1);
+    bool any = false;
+    for (size_t k = n_main; k < p->launches_grad.size() && e == hipSuccess; ++k)
+      if (p->launches_grad[k].n_wu <= round) any = p->launches_grad[k].side = true;
+    if (any && e == hipSuccess) e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+    if (any && e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+    if (any && e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+  }
   if (e == hipSuccess && scan_ch > 0) e = prepare_grad_scan(scan_ch);
   if (e == hipSuccess) e = prepare_reduce(p->max_rows);
 

@@ -95,7 +95,7 @@ bool same(const nr_plan_options& x, const nr_plan_options& y) {
   for (int k = 0; k < NR_NUM_BUCKETS; ++k)
     if (x.grad_variant[k] != y.grad_variant[k]) return false;
   return x.xcd_run == y.xcd_run && x.pack_tails == y.pack_tails &&
-         x.split_tails == y.split_tails;
+         x.split_tails == y.split_tails && x.side_stream == y.side_stream;
 }
 
 }  // namespace
@@ -180,6 +180,11 @@ extern "C" nr_status nr_autotune(const nr_batch_desc* d, const nr_values* v, int
   for (int bit : {NR_TAILS_LONE, NR_TAILS_SPLIT}) {
     nr_plan_options o = best;
     o.split_tails ^= bit;
+    if ((st = consider(o)) != NR_OK) return st;
+  }
+  {
+    nr_plan_options o = best;
+    o.side_stream = 1 - o.side_stream;
     if ((st = consider(o)) != NR_OK) return st;
   }
 

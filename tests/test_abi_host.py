@@ -149,15 +149,17 @@ def test_plan_options_defaults_and_dict():
     from paper_2509_06924_amd import plan_options
     o = plan_options()
     assert list(o.grad_variant) == [n.NR_VARIANT_AUTO] * n.NR_NUM_BUCKETS
-    assert o.xcd_run == 8 and o.pack_tails == 1 and o.split_tails == 3
+    assert o.xcd_run == 8 and o.pack_tails == 1 and o.split_tails == 3 and o.side_stream == 1
     o = plan_options({"grad_variant": {"10": n.NR_VARIANT_RECOMPUTE}, "xcd_run": 4,
-                      "pack_tails": 0})
+                      "pack_tails": 0, "side_stream": 0})
     k10 = [L.nr_bucket_lmax(k) for k in range(n.NR_NUM_BUCKETS)].index(10)
     assert o.grad_variant[k10] == n.NR_VARIANT_RECOMPUTE and o.xcd_run == 4 and o.pack_tails == 0
+    assert o.side_stream == 0
 
 
-@pytest.mark.parametrize("case", ["xcd_zero", "xcd_big", "pack_two", "split_two", "variant_unknown",
-                                  "store_too_deep_f64", "store_too_deep_f32"])
+@pytest.mark.parametrize("case", ["xcd_zero", "xcd_big", "pack_two", "split_two", "side_two",
+                                  "side_negative", "variant_unknown", "store_too_deep_f64",
+                                  "store_too_deep_f32"])
 def test_invalid_plan_options_rejected(case):
     n, L = _lib()
     from paper_2509_06924_amd import plan_options
@@ -172,6 +174,10 @@ def test_invalid_plan_options_rejected(case):
         o.pack_tails = 2
     elif case == "split_two":
         o.split_tails = 4
+    elif case == "side_two":
+        o.side_stream = 2
+    elif case == "side_negative":
+        o.side_stream = -1
     elif case == "variant_unknown":
         o.grad_variant[0] = 9
     elif case == "store_too_deep_f64":

@@ -53,6 +53,8 @@ def _check_against_oracle(nr, orc, batch, options):
     {"split_tails": 1},
     {"split_tails": 2, "pack_tails": 0,
      "grad_variant": {str(k): 2 for k in (1, 2, 4, 6, 8, 10)}},
+    {"side_stream": 0},
+    {"side_stream": 0, "split_tails": 0, "pack_tails": 0},
 ])
 def test_schedules_match_oracle(nr, orc, options):
     _check_against_oracle(nr, orc, _batch(501), options)
@@ -63,7 +65,7 @@ def test_autotune_choice_and_cache(nr, orc, tmp_path):
     batch = inputs.c2_batched(n_items=512, L=6)
     cache = str(tmp_path / "tune.json")
     opts = autotune.tune(batch, cache=cache, reps=2)
-    assert set(opts) == {"grad_variant", "xcd_run", "pack_tails", "split_tails"}
+    assert set(opts) == {"grad_variant", "xcd_run", "pack_tails", "split_tails", "side_stream"}
     assert autotune.tune(batch, cache=cache) == opts  # served from the cache
     p_def = nr.Problem.from_batch(batch)
     p_tun = nr.Problem.from_batch(batch, options=opts)
