@@ -281,11 +281,29 @@ nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st, b
   // them on st); join: st waits for the side stream's launches
   const bool fork = grad && p->side != nullptr;
   std::unique_lock<std::mutex> lock;
+  // A call being captured into a graph gets fresh events of its own, so that
+  // no event object is shared between captured and eager fork/joins.
+  hipEvent_t ev_fork = p->ev_fork, ev_join = p->ev_join;
+  bool own_events = false;
   if (fork) {
     lock = std::unique_lock<std::mutex>(p->side_mu);
-    hipError_t e = hipEventRecord(p->ev_fork, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_fork, 0);
-    if (e != hipSuccess) return hip_fail(e, "side stream fork");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e == hipSuccess && cs != hipStreamCaptureStatusNone) {
+      own_events = true;
+      ev_fork = ev_join = nullptr;
+      e = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_join, hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev_fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->side, ev_fork, 0);
+    if (e != hipSuccess) {
+      if (own_events) {
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+      }
+      return hip_fail(e, "side stream fork");
+    }
   }
   hipError_t launch_err = hipSuccess;
   for (const Launch& L : grad ? p->launches_grad : p->launches_fwd) {
@@ -309,8 +327,12 @@ nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st, b
   }
   if (fork) {
     // joined even after a failed launch, so that a capture stays well formed
-    hipError_t e = hipEventRecord(p->ev_join, p->side);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, p->ev_join, 0);
+    hipError_t e = hipEventRecord(ev_join, p->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, ev_join, 0);
+    if (own_events) {
+      (void)hipEventDestroy(ev_fork);
+      (void)hipEventDestroy(ev_join);
+    }
     if (e != hipSuccess && launch_err == hipSuccess) return hip_fail(e, "side stream join");
   }
   if (launch_err != hipSuccess) return hip_fail(launch_err, "kernel launch");
