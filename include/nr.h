@@ -169,14 +169,15 @@ nr_status nr_plan_create(const nr_batch_desc* desc, nr_plan** plan_out);
  *                       groups of smearing nodes (lane = node group x point;
  *                       12 to 32 points).
  *     Other tails follow pack_tails.  Default: both bits.
- *   side_stream: 1 (default) runs the gradient's tail and split launches
- *     that hold at most one round of the device (two waves per SIMD of
- *     every compute unit) on a second stream that the plan owns (default
- *     priority, non-blocking), forked from the caller's stream after the
- *     per-layer constants and joined back before the reduction, so that
- *     those small launches run beside the full-unit launches instead of
- *     leaving most of the device idle after them; 0 keeps every launch on
- *     the caller's stream.  The fork and join are event waits, so
+ *   side_stream: 1 (default) runs every second full-unit launch of the
+ *     gradient (one launch per layer-count bucket) and its tail and split
+ *     launches that hold at most one round of the device (two waves per
+ *     SIMD of every compute unit) on a second stream that the plan owns
+ *     (default priority, non-blocking), forked from the caller's stream
+ *     after the per-layer constants and joined back before the reduction:
+ *     small launches run beside the full-unit launches instead of leaving
+ *     most of the device idle after them, and consecutive buckets overlap;
+ *     0 keeps every launch on the caller's stream.  The fork and join are event waits, so
  *     calls stay ordered on the caller's stream and can be captured into a
  *     HIP graph (the side stream joins the capture).  Calls on one plan from
  *     several host threads are serialised around the fork and join. */

@@ -933,11 +933,15 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
   // SIMD) leave most of it idle when they run after the full units; on the
   // side stream they run beside them.  Larger ones gain nothing there and
   // only interfere (the 4096-draw batch's 4096 split units: 2 % slower).
+  // Every second full-unit launch (one per layer-count bucket, deepest first)
+  // goes there too, so that one bucket's last waves overlap the next bucket's
+  // first (16384-item ragged batch: 1.8 % faster in FP64).
   if (e == hipSuccess && p->opts.side_stream && n_main > 0) {
     int cus = 0;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
     const int round = 2 * 4 * std::max(cus, 1);
     bool any = false;
+    for (size_t k = 1; k < n_main; k += 2) any = p->launches_grad[k].side = true;
     for (size_t k = n_main; k < p->launches_grad.size() && e == hipSuccess; ++k)
       if (p->launches_grad[k].n_wu <= round) any = p->launches_grad[k].side = true;
     if (any && e == hipSuccess) e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
