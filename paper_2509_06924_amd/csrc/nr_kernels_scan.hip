@@ -149,16 +149,21 @@ __global__ __launch_bounds__(64) void k_loglik_grad_scan(KernelArgs a) {
     const double kz0sq = kz0_squared(q);
     const cd kz0 = fronting_kz<F64>(q);
 
-    // 1. the chunk product, applied to both columns bottom-up
+    // 1. the chunk product, applied to both columns bottom-up; each level's
+    //    r' and e are kept in its tape slot for the re-run in step 3
     M2 X = m2_identity();
     if (own) {
-      cd kzn = medium_root(L, kz0sq, hi).kz;
+      cd kzn = medium_root(L, kz0sq, hi, edge).kz;
 #pragma unroll
       for (int t = CHT - 1; t >= 0; --t) {
         if (t < n) {
           const int jj = lo + t;
-          const cd kzc = (jj == 0) ? kz0 : medium_root(L, kz0sq, jj).kz;
+          const cd kzc = (jj == 0) ? kz0 : medium_root(L, kz0sq, jj, edge).kz;
           const Lvl lv = level_coeffs(s.tab, L, jj, kzc, kzn);
+          TP(t, 0) = lv.it.rp.re;
+          TP(t, 1) = lv.it.rp.im;
+          TP(t, 2) = lv.e.re;
+          TP(t, 3) = lv.e.im;
           const cd a0 = X.a + lv.it.rp * X.c, b0 = X.b + lv.it.rp * X.d;
           X.c = lv.e * (lv.it.rp * X.a + X.c);
           X.d = lv.e * (lv.it.rp * X.b + X.d);
@@ -198,25 +203,22 @@ __global__ __launch_bounds__(64) void k_loglik_grad_scan(KernelArgs a) {
     }
     if (!own) continue;
 
-    // 3. the lane's forward sweep (state tape) and adjoint
+    // 3. the lane's forward sweep from its entering state with the r' and e
+    //    of step 1; each slot then holds the state entering its level
     {
       cd Pv = Ps, Qv = Qs;
-      cd kzn = medium_root(L, kz0sq, hi, edge).kz;
 #pragma unroll
       for (int t = CHT - 1; t >= 0; --t) {
         if (t < n) {
-          const int jj = lo + t;
+          const cd rp = mk(TP(t, 0), TP(t, 1));
+          const cd e = mk(TP(t, 2), TP(t, 3));
           TP(t, 0) = Pv.re;
           TP(t, 1) = Pv.im;
           TP(t, 2) = Qv.re;
           TP(t, 3) = Qv.im;
-          const cd kzc = (jj == 0) ? kz0 : medium_root(L, kz0sq, jj, edge).kz;
-          const Lvl lv = level_coeffs(s.tab, L, jj, kzc, kzn);
-          const cd Pn = Pv + lv.it.rp * Qv;
-          const cd tt = lv.it.rp * Pv + Qv;
-          Qv = (jj >= 1) ? lv.e * tt : tt;
+          const cd Pn = Pv + rp * Qv;
+          Qv = e * (rp * Pv + Qv);  // e = 1 at level 0
           Pv = Pn;
-          kzn = kzc;
         }
       }
     }
