@@ -89,3 +89,44 @@ def test_side_stream_leapfrog_graph_replays_equal_eager(nr, torch_cuda):
         _ = (st_e.layers * 2.0).sum().item()
         _ = prob_g.loglik_grad()
     graph.close()
+
+
+def test_side_stream_calls_from_two_host_threads(nr, torch_cuda):
+    """Two host threads call nr_loglik_grad on one plan, each with its own
+    stream, workspace and outputs: the plan's side stream and its fork ...
+    join sequence are shared, and every result equals a one-thread call."""
+    import threading
+    torch = torch_cuda
+    from paper_2509_06924_amd import NR_OP_LOGLIK_GRAD, nr_loglik_grad
+    batch = _tail_batch(902)
+    prob = nr.Problem.from_batch(batch, options={"side_stream": 1})
+    ref = prob.loglik_grad()
+    torch.cuda.synchronize()
+    n_words = max(1, (prob.plan.workspace_size(NR_OP_LOGLIK_GRAD) + 7) // 8)
+    vals = prob.values()
+    n_calls = 12
+    results, errors = {}, []
+
+    def worker(tid):
+        try:
+            s = torch.cuda.Stream()
+            ws = torch.empty(n_words, dtype=torch.float64, device=prob.device)
+            outs = [tuple(torch.empty_like(t) for t in ref) for _ in range(n_calls)]
+            for o in outs:
+                nr_loglik_grad(prob.plan, vals, o[0], o[1], o[2], ws, stream=s)
+            s.synchronize()
+            results[tid] = outs
+        except Exception as exc:  # reported below, on the test's thread
+            errors.append(repr(exc))
+
+    threads = [threading.Thread(target=worker, args=(t,)) for t in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for tid, outs in results.items():
+        for k, o in enumerate(outs):
+            for a, b in zip(o, ref):
+                assert torch.equal(a, b), f"thread {tid} call {k}"
