@@ -52,8 +52,20 @@ __global__ __launch_bounds__(256) void k_reduce_loglik(ReduceArgs a) {
   if (b >= a.n_items) return;
   const int64_t first = a.item_wu_first[b];
   const int cnt = a.item_wu_count[b];
+  // eight offsets, then their eight records, per round: independent loads
+  // instead of a chain of dependent ones; the sum runs over the units in order
   double s = 0.0;
-  for (int k = 0; k < cnt; ++k) s += a.rec[a.rec_of_wu[first + k]];
+  for (int k0 = 0; k0 < cnt; k0 += 8) {
+    int64_t o[8];
+    double r[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o[j] = (k0 + j < cnt) ? a.rec_of_wu[first + k0 + j] : 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r[j] = (k0 + j < cnt) ? a.rec[o[j]] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (k0 + j < cnt) s += r[j];
+  }
   a.logL[b] = s;
 }
 
@@ -70,11 +82,24 @@ __global__ __launch_bounds__(64) void k_reduce_grad(ReduceArgs a) {
   // records hold 4 + 4 NR doubles; the last is written by the resolution
   // form only
   const int nf = (a.g_res ? 4 : 3) + 4 * NR;
-  for (int f = lane; f < nf; f += 64) {
-    double v = 0.0;
-    for (int k = 0; k < cnt; ++k) v += a.rec[a.rec_of_wu[first + k] + f];
-    fsum[f] = v;
+  // The units' record offsets are staged 64 at a time (one load per lane),
+  // so the record loads of a chunk are independent of each other instead of
+  // each waiting for its offset; the sum runs over the units in order.
+  __shared__ int64_t offs[64];
+  for (int k0 = 0; k0 < cnt; k0 += 64) {
+    const int kc = min(64, cnt - k0);
+    __syncthreads();  // the previous chunk's offsets are no longer read
+    if (lane < kc) offs[lane] = a.rec_of_wu[first + k0 + lane];
+    __syncthreads();
+    for (int f = lane; f < nf; f += 64) {
+      double v = (k0 == 0) ? 0.0 : fsum[f];
+#pragma unroll 8
+      for (int k = 0; k < kc; ++k) v += a.rec[offs[k] + f];
+      fsum[f] = v;
+    }
   }
+  if (cnt <= 0)
+    for (int f = lane; f < nf; f += 64) fsum[f] = 0.0;
   __syncthreads();
   const double* rows = a.layers + 4 * roff;
   double* g = a.g_rows + 4 * roff;
