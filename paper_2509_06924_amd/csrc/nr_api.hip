@@ -169,7 +169,8 @@ struct nr_plan {
   std::vector<void*> owned;
   // second stream for the gradient's tail and split launches (side_stream)
   hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;          // eager calls
+  hipEvent_t ev_fork_cap = nullptr, ev_join_cap = nullptr;  // calls under graph capture
   mutable std::mutex side_mu;  // one fork ... join sequence at a time
 };
 
@@ -179,10 +180,10 @@ void plan_free(nr_plan* p) {
   for (void* ptr : p->owned)
     if (ptr) (void)hipFree(ptr);
   p->owned.clear();
-  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
-  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+  for (hipEvent_t ev : {p->ev_fork, p->ev_join, p->ev_fork_cap, p->ev_join_cap})
+    if (ev) (void)hipEventDestroy(ev);
   if (p->side) (void)hipStreamDestroy(p->side);
-  p->ev_fork = p->ev_join = nullptr;
+  p->ev_fork = p->ev_join = p->ev_fork_cap = p->ev_join_cap = nullptr;
   p->side = nullptr;
 }
 
@@ -281,29 +282,20 @@ nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st, b
   // them on st); join: st waits for the side stream's launches
   const bool fork = grad && p->side != nullptr;
   std::unique_lock<std::mutex> lock;
-  // A call being captured into a graph gets fresh events of its own, so that
+  // A call being captured into a graph uses an event pair of its own, so that
   // no event object is shared between captured and eager fork/joins.
   hipEvent_t ev_fork = p->ev_fork, ev_join = p->ev_join;
-  bool own_events = false;
   if (fork) {
     lock = std::unique_lock<std::mutex>(p->side_mu);
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     hipError_t e = hipStreamIsCapturing(st, &cs);
     if (e == hipSuccess && cs != hipStreamCaptureStatusNone) {
-      own_events = true;
-      ev_fork = ev_join = nullptr;
-      e = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_join, hipEventDisableTiming);
+      ev_fork = p->ev_fork_cap;
+      ev_join = p->ev_join_cap;
     }
     if (e == hipSuccess) e = hipEventRecord(ev_fork, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(p->side, ev_fork, 0);
-    if (e != hipSuccess) {
-      if (own_events) {
-        if (ev_fork) (void)hipEventDestroy(ev_fork);
-        if (ev_join) (void)hipEventDestroy(ev_join);
-      }
-      return hip_fail(e, "side stream fork");
-    }
+    if (e != hipSuccess) return hip_fail(e, "side stream fork");
   }
   hipError_t launch_err = hipSuccess;
   for (const Launch& L : grad ? p->launches_grad : p->launches_fwd) {
@@ -329,10 +321,6 @@ nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st, b
     // joined even after a failed launch, so that a capture stays well formed
     hipError_t e = hipEventRecord(ev_join, p->side);
     if (e == hipSuccess) e = hipStreamWaitEvent(st, ev_join, 0);
-    if (own_events) {
-      (void)hipEventDestroy(ev_fork);
-      (void)hipEventDestroy(ev_join);
-    }
     if (e != hipSuccess && launch_err == hipSuccess) return hip_fail(e, "side stream join");
   }
   if (launch_err != hipSuccess) return hip_fail(launch_err, "kernel launch");
@@ -947,6 +935,8 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
     if (any && e == hipSuccess) e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
     if (any && e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
     if (any && e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+    if (any && e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork_cap, hipEventDisableTiming);
+    if (any && e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join_cap, hipEventDisableTiming);
   }
   if (e == hipSuccess && scan_ch > 0) e = prepare_grad_scan(scan_ch);
   if (e == hipSuccess) e = prepare_reduce(p->max_rows);
