@@ -519,8 +519,8 @@ def hmc_driver_row(nr, n_leapfrog=4):
 
 def deep_stack_row(nr, reps=3):
     """64 microsliced profiles x 1000 slabs x 200 Q, 5% dQ/Q: logL + gradient
-    through the parallel-in-layers scan (one wave per data point), and the
-    forward-only value kernel on the same batch."""
+    through the parallel-in-layers scan (two waves per data point at this
+    depth), and the forward-only value kernel on the same batch."""
     import torch
 
     from paper_2509_06924_amd import inputs
@@ -532,7 +532,7 @@ def deep_stack_row(nr, reps=3):
     dtf = _timed(lambda: prob.loglik(stream=stream), reps)
     ls = batch.layer_steps()
     return {"what": "64 microsliced profiles x 1000 slabs x 200 Q, 5% dQ/Q: parallel-in-layers "
-                    "scan gradient (FP64), one wave per data point",
+                    "scan gradient (FP64), two waves per data point",
             "ms_per_step": dt * 1e3, "value": ls / dt, "unit": UNIT,
             "frac_fp64_peak": FLOP_PER_LAYER_STEP * ls / dt / FP64_VALU_PEAK,
             "forward_only_ms": dtf * 1e3, "layer_steps_per_step": ls}

@@ -95,7 +95,7 @@ struct Launch {
   bool store = false;  // gradient: store variant (else recompute)
   bool tail = false;
   bool split = false;  // split tail units (one item's partial group, lanes over node groups)
-  int scan_ch = 0;     // deep list: the largest levels-per-lane of its items
+  int scan_ch = 0;     // deep lists: the largest levels-per-lane of its items at 64 lanes
   bool side = false;   // runs on the plan's side stream
   int n_wu = 0;
   int32_t* item = nullptr;      // [n_wu]: the unit's item (first item for tails)
@@ -697,10 +697,16 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
     int32_t item, p0, count;
     int64_t rec0;  // record of its first point
   };
-  // one list per bucket, then the deep list (kDeepBucket)
-  std::vector<std::vector<Wu>> fwd_units(kNumBuckets + 1), grad_units(kNumBuckets + 1);
+  // one list per bucket, then the deep lists: forward one (kDeepBucket),
+  // gradient three (kDeepBucket + c), by the levels per lane an item needs at
+  // 64 lanes (c = 0: up to 8, 1: up to 16, 2: more), which set the waves per
+  // data point of the scan kernel (1, 2, 4), so that shallower deep items do
+  // not run with the idle lanes of the deepest one
+  constexpr int kDeepClasses = 3;
+  std::vector<std::vector<Wu>> fwd_units(kNumBuckets + 1);
+  std::vector<std::vector<Wu>> grad_units(kNumBuckets + kDeepClasses);
   std::vector<std::vector<Wu>> split_units(kNumBuckets);
-  int scan_ch = 0;
+  int scan_ch[kDeepClasses] = {0, 0, 0};
   std::map<std::pair<int, int>, std::vector<Tail>> tails;  // (depth, nodes)
   std::vector<int64_t> ll_first(nI), ll_offs, gr_first(nI), gr_offs;
   std::vector<int32_t> ll_count(nI), gr_count(nI);
@@ -724,12 +730,14 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
     }
     p->max_rows = std::max(p->max_rows, N + 2);
     if (bk == kDeepBucket) {
-      // one unit per data point; the wave splits the layers
+      // one unit per data point; its lanes split the layers
       gr_first[b] = (int64_t)gr_offs.size();
       gr_count[b] = (int32_t)nq;
-      scan_ch = std::max(scan_ch, (N + 1 + 63) / 64);
+      const int ch64 = (N + 1 + 63) / 64;
+      const int cls = ch64 <= 8 ? 0 : ch64 <= 16 ? 1 : 2;
+      scan_ch[cls] = std::max(scan_ch[cls], ch64);
       for (int64_t k = 0; k < nq; ++k) {
-        grad_units[bk].push_back({b, (int32_t)k, rec_gr, (double)K * (N + 1) * 64});
+        grad_units[kDeepBucket + cls].push_back({b, (int32_t)k, rec_gr, (double)K * (N + 1) * 64});
         gr_offs.push_back(rec_gr);
         rec_gr += rsz;
       }
@@ -899,9 +907,9 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
         sc[k] = v[src].split;
       }
       Launch L;
-      L.bucket = bk;
+      L.bucket = std::min(bk, kDeepBucket);
       L.store = bk < kNumBuckets && p->bucket_store[bk];
-      L.scan_ch = bk == kDeepBucket ? scan_ch : 0;
+      L.scan_ch = bk >= kDeepBucket ? std::max(scan_ch[bk - kDeepBucket], 1) : 0;
       L.split = split;
       L.n_wu = (int)v.size();
       e = upload(&L.item, it);
@@ -938,7 +946,8 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
     if (any && e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork_cap, hipEventDisableTiming);
     if (any && e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join_cap, hipEventDisableTiming);
   }
-  if (e == hipSuccess && scan_ch > 0) e = prepare_grad_scan(scan_ch);
+  for (int c = 0; c < kDeepClasses && e == hipSuccess; ++c)
+    if (scan_ch[c] > 0) e = prepare_grad_scan(scan_ch[c]);
   if (e == hipSuccess) e = prepare_reduce(p->max_rows);
 
   if (e != hipSuccess) {

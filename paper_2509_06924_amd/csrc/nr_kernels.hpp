@@ -159,18 +159,23 @@ struct Shared {
 typedef __attribute__((address_space(3))) const volatile double lds_cv_double;
 __device__ __forceinline__ double ld(const double& x) { return *(lds_cv_double*)(&x); }
 
-__device__ __forceinline__ void stage_shared(Shared& s, int lane, const double* rule) {
-  if (lane < kSmearNodes) {
-    s.t[lane] = rule[lane];
-    s.w[lane] = rule[kSmearNodes + lane];
+// (write: the lanes of one wave fill the tables; every thread of the block
+// reaches the barrier)
+__device__ __forceinline__ void stage_shared(Shared& s, int lane, const double* rule,
+                                             bool write = true) {
+  if (write) {
+    if (lane < kSmearNodes) {
+      s.t[lane] = rule[lane];
+      s.w[lane] = rule[kSmearNodes + lane];
+    }
+    // tables follow the rule in the same device buffer
+    const double* tb = rule + 2 * kSmearNodes;
+    s.tab.sc[lane][0] = tb[2 * lane];
+    s.tab.sc[lane][1] = tb[2 * lane + 1];
+    s.tab.sc[lane + 64][0] = tb[2 * lane + 128];
+    s.tab.sc[lane + 64][1] = tb[2 * lane + 129];
+    s.tab.e2[lane] = tb[256 + lane];
   }
-  // tables follow the rule in the same device buffer
-  const double* tb = rule + 2 * kSmearNodes;
-  s.tab.sc[lane][0] = tb[2 * lane];
-  s.tab.sc[lane][1] = tb[2 * lane + 1];
-  s.tab.sc[lane + 64][0] = tb[2 * lane + 128];
-  s.tab.sc[lane + 64][1] = tb[2 * lane + 129];
-  s.tab.e2[lane] = tb[256 + lane];
   __syncthreads();
 }
 

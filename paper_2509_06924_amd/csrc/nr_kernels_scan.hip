@@ -1,20 +1,24 @@
 // Gradient kernel for deep stacks (more than NR_MAX_LAYERS layers, e.g.
 // microsliced SLD profiles): the layer product is split across the 64 lanes
 // of a wave and combined by an associative scan of 2x2 transfer matrices; the
-// adjoint runs as the reverse scan.  One wave per (item, data point); the
-// point's smearing nodes are processed in turn.
+// adjoint runs as the reverse scan.  One workgroup of NW waves per (item,
+// data point), NT = 64 NW lanes; the point's smearing nodes are processed in
+// turn.
 //
 // In the scaled form the state entering level j maps to the state leaving it
 // by T_j = [[1, r'_j], [e_j r'_j, e_j]] (e_0 = 1), so the top state is
 // T_0 T_1 ... T_N (1, 0)^T and r = Qv / P.  Lane l owns the levels
-// [l CH, (l + 1) CH) (CH = ceil((N + 1) / 64)) and the media of those levels:
+// [l CH, (l + 1) CH) (CH = ceil((N + 1) / NT)) and the media of those levels:
 //   1. its chunk product M_l = T_{l CH} ... T_{(l+1) CH - 1} (two columns);
-//   2. an inclusive suffix scan U_l = M_l ... M_63 gives the state entering
-//      each chunk from below (column 0 of U_{l+1}) and the top state (U_0);
+//   2. an inclusive suffix scan U_l = M_l ... M_{NT-1} gives the state
+//      entering each chunk from below (column 0 of U_{l+1}) and the top
+//      state (U_0);
 //      an inclusive prefix scan W_l = M_0 ... M_l gives, with V_l = W_{l-1},
 //      the cotangent of the state leaving the chunk at its top, V_l^H c_0
 //      (the cotangent of a linear map's input is its conjugate transpose
-//      applied to the output's cotangent);
+//      applied to the output's cotangent).  Each wave scans its own lanes
+//      with shuffles; across waves the scans are completed with the waves'
+//      chunk-product totals, exchanged through LDS;
 //   3. the lane's own forward sweep from its entering state (the state tape,
 //      in registers or LDS) and the level-by-level adjoint of the shallow
 //      kernels.
@@ -83,33 +87,49 @@ __device__ __forceinline__ Lvl level_coeffs(const MathTables& T, const Layers<F6
 }  // namespace
 
 // Per-lane storage of the state tape (the state entering each of the lane's
-// levels) and of the accumulators (Hw re, Hw im, Hd, Hs per medium slot; slot
-// t is medium lo + t, slot n = hi - lo the lane's lower boundary medium):
-// registers where they fit, else LDS in lane-interleaved planes.
-template <int CHT, bool IN_LDS>
+// levels; between steps 1 and 3, the level's r' and e) and of the
+// accumulators (Hw re, Hw im, Hd, Hs per medium slot; slot t is medium lo + t,
+// slot n = hi - lo the lane's lower boundary medium): registers, or LDS in
+// planes interleaved over the NT lanes of a data point.
+template <int CHT, bool IN_LDS, int NT>
 struct LaneTape {
   double r[IN_LDS ? 1 : CHT][4];
-  __device__ __forceinline__ double& at(double* lds, int lane, int t, int f) {
+  __device__ __forceinline__ double& at(double* lds, int gl, int t, int f) {
     if constexpr (IN_LDS)
-      return lds[(t * 4 + f) * 64 + lane];
+      return lds[(t * 4 + f) * NT + gl];
     else
       return r[t][f];
   }
 };
 
-// CHT: the largest levels-per-lane the launch's items need (1 .. 32).
-template <int CHT, bool RES>
-__global__ __launch_bounds__(64) void k_loglik_grad_scan(KernelArgs a) {
+__device__ __forceinline__ M2 load_m2(const cd* x) {
+  M2 z;
+  z.a = x[0];
+  z.b = x[1];
+  z.c = x[2];
+  z.d = x[3];
+  return z;
+}
+
+// CHT: the largest levels-per-lane the launch's items need (1, 2, 4 or 8);
+// NW: waves per data point (1, 2 or 4).
+template <int CHT, int NW, bool RES>
+__global__ __launch_bounds__(64 * NW, 2) void k_loglik_grad_scan(KernelArgs a) {
+  constexpr int NT = 64 * NW;
   constexpr bool kTapeLds = CHT >= 8;
-  constexpr bool kAccLds = CHT >= 32;
   __shared__ Shared s;
-  __shared__ double tape_lds[kTapeLds ? CHT * 4 * 64 : 1];
-  __shared__ double acc_lds[kAccLds ? (CHT + 1) * 4 * 64 : 1];
-  LaneTape<CHT, kTapeLds> tape;
-  LaneTape<CHT + 1, kAccLds> accs;
-  const int lane = threadIdx.x;
-  auto TP = [&](int t, int f) -> double& { return tape.at(tape_lds, lane, t, f); };
-  auto AC = [&](int t, int f) -> double& { return accs.at(acc_lds, lane, t, f); };
+  __shared__ double tape_lds[kTapeLds ? CHT * 4 * NT : 1];
+  // per wave: the product of its lanes' chunks, its last lane's boundary
+  // slot and its part of the resolution derivative
+  __shared__ cd xt[NW][4];
+  __shared__ double xb[NW][5];
+  LaneTape<CHT, kTapeLds, NT> tape;
+  LaneTape<CHT + 1, false, NT> accs;
+  const int gl = threadIdx.x;  // lane of the data point
+  const int lane = gl & 63;    // lane of the wave
+  const int wv = gl >> 6;      // wave of the data point
+  auto TP = [&](int t, int f) -> double& { return tape.at(tape_lds, gl, t, f); };
+  auto AC = [&](int t, int f) -> double& { return accs.at(nullptr, gl, t, f); };
 
   const int w = blockIdx.x;
   const int item = a.wu_item[w];
@@ -119,11 +139,11 @@ __global__ __launch_bounds__(64) void k_loglik_grad_scan(KernelArgs a) {
   const int64_t roff = a.row_off[item];
   const int N = (int)(a.row_off[item + 1] - roff) - 2;
   const int NL = N + 1;  // levels 0..N
-  const int CH = (NL + 63) / 64;
-  const int lo = min(lane * CH, NL), hi = min(lo + CH, NL);
+  const int CH = (NL + NT - 1) / NT;
+  const int lo = min(gl * CH, NL), hi = min(lo + CH, NL);
   const int n = hi - lo;  // levels of this lane (0 .. CH <= CHT)
   const bool own = n > 0;
-  stage_shared(s, lane, a.rule);
+  stage_shared(s, lane, a.rule, wv == 0);
 #pragma unroll
   for (int t = 0; t <= CHT; ++t)
 #pragma unroll
@@ -173,7 +193,7 @@ __global__ __launch_bounds__(64) void k_loglik_grad_scan(KernelArgs a) {
         }
       }
     }
-    // 2. suffix and prefix scans across the lanes
+    // 2. suffix and prefix scans across the wave's lanes ...
     M2 U = X, W = X;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -182,9 +202,43 @@ __global__ __launch_bounds__(64) void k_loglik_grad_scan(KernelArgs a) {
       if (lane + off < 64) U = m2_mul(U, Yu);
       if (lane >= off) W = m2_mul(Yw, W);
     }
-    const M2 Ub = shfl_m2(U, lane < 63 ? lane + 1 : 63);
-    const M2 V = shfl_m2(W, lane > 0 ? lane - 1 : 0);
-    const cd P0 = shfl_cd(U.a, 0), Q0 = shfl_cd(U.c, 0);
+    // ... and across the waves: with T_v the product of wave v's chunks,
+    // U_l = U_l(wave) T_{wv+1} ... T_{NW-1}, W_l = T_0 ... T_{wv-1} W_l(wave)
+    M2 Ub, V;
+    cd P0, Q0;
+    if constexpr (NW == 1) {
+      Ub = shfl_m2(U, lane < 63 ? lane + 1 : 63);
+      V = shfl_m2(W, lane > 0 ? lane - 1 : 0);
+      P0 = shfl_cd(U.a, 0);
+      Q0 = shfl_cd(U.c, 0);
+    } else {
+      if (lane == 0) {
+        xt[wv][0] = U.a;
+        xt[wv][1] = U.b;
+        xt[wv][2] = U.c;
+        xt[wv][3] = U.d;
+      }
+      __syncthreads();
+      M2 S = m2_identity(), Pp = m2_identity(), F = load_m2(xt[0]);
+#pragma unroll
+      for (int v = NW - 1; v >= 1; --v)
+        if (v > wv) S = m2_mul(load_m2(xt[v]), S);
+#pragma unroll
+      for (int v = 0; v < NW - 1; ++v)
+        if (v < wv) Pp = m2_mul(Pp, load_m2(xt[v]));
+      // the top state, formed in the same order by every lane
+#pragma unroll
+      for (int v = 1; v < NW; ++v) F = m2_mul(F, load_m2(xt[v]));
+      __syncthreads();  // xt is written again at the next node
+      U = m2_mul(U, S);
+      W = m2_mul(Pp, W);
+      Ub = shfl_m2(U, lane < 63 ? lane + 1 : 63);
+      V = shfl_m2(W, lane > 0 ? lane - 1 : 0);
+      if (lane == 63) Ub = S;  // the next wave's first lane
+      if (lane == 0) V = Pp;   // the previous wave's last lane
+      P0 = F.a;
+      Q0 = F.c;
+    }
     const cd iP = crecip(P0);
     const cd r = Q0 * iP;
     Rsm += wk * cabs2(r);
@@ -192,12 +246,12 @@ __global__ __launch_bounds__(64) void k_loglik_grad_scan(KernelArgs a) {
     const cd Pb0 = cmulc(-(r * iP), rbar);
     const cd Qb0 = cmulc(iP, rbar);
     cd Pb = Pb0, Qb = Qb0;
-    if (lane > 0) {
+    if (gl > 0) {
       Pb = cmulc(V.a, Pb0) + cmulc(V.c, Qb0);
       Qb = cmulc(V.b, Pb0) + cmulc(V.d, Qb0);
     }
     cd Ps = mk(1.0, 0.0), Qs = mk(0.0, 0.0);
-    if (lane < 63) {
+    if (gl < NT - 1) {
       Ps = Ub.a;
       Qs = Ub.c;
     }
@@ -275,7 +329,7 @@ __global__ __launch_bounds__(64) void k_loglik_grad_scan(KernelArgs a) {
     if constexpr (RES) Hq = fma(0.5 * q * dq_dres * tk, sw, Hq);
   }
 
-  // ---- the point's likelihood and seed (lane-uniform) ----
+  // ---- the point's likelihood and seed (uniform over the lanes) ----
   const int NR = N + 2;
   const double sc = a.scale[item];
   const double Rhat = sc * Rsm + a.bkg[item];
@@ -303,11 +357,28 @@ __global__ __launch_bounds__(64) void k_loglik_grad_scan(KernelArgs a) {
     if (t == n)
 #pragma unroll
       for (int f = 0; f < 4; ++f) bnd[f] = AC(t, f);
+  double from_above[4];
 #pragma unroll
-  for (int f = 0; f < 4; ++f) {
-    const double from_above = __shfl(bnd[f], lane > 0 ? lane - 1 : 0, 64);
-    if (own && lane > 0) AC(0, f) += from_above;
+  for (int f = 0; f < 4; ++f) from_above[f] = __shfl(bnd[f], lane > 0 ? lane - 1 : 0, 64);
+  double hq = RES ? wave_sum(Hq) : 0.0;
+  if constexpr (NW > 1) {
+    if (lane == 63)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) xb[wv][f] = bnd[f];
+    if (lane == 0) xb[wv][4] = hq;
+    __syncthreads();
+    if (lane == 0 && wv > 0)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) from_above[f] = xb[wv - 1][f];
+    if constexpr (RES) {
+      hq = 0.0;
+#pragma unroll
+      for (int v = 0; v < NW; ++v) hq += xb[v][4];
+    }
   }
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+    if (own && gl > 0) AC(0, f) += from_above[f];
   if (own) {
 #pragma unroll
     for (int t = 0; t < CHT; ++t) {
@@ -326,8 +397,7 @@ __global__ __launch_bounds__(64) void k_loglik_grad_scan(KernelArgs a) {
       rec[3 + 3 * NR + NL] = fac * bnd[3];
     }
   }
-  const double hq = RES ? wave_sum(Hq) : 0.0;
-  if (lane == 0) {
+  if (gl == 0) {
     rec[0] = ll;
     rec[1] = ghat * Rsm;
     rec[2] = ghat;
@@ -335,44 +405,52 @@ __global__ __launch_bounds__(64) void k_loglik_grad_scan(KernelArgs a) {
   }
 }
 
-// The kernel instance for a launch: levels-per-lane rounded up to a power of
-// two (register tape up to 4, register accumulators up to 16).
-static int scan_cht(int ch_max) {
+// The configuration of a launch whose deepest item needs ch64 levels per
+// lane at 64 lanes: one wave per data point up to 8 levels per lane, else two
+// or four waves, so that no lane holds more than 8 levels (the tape then fits
+// 2 KB of LDS per level and wave, and the kernel two waves per SIMD); the
+// levels per lane round up to a power of two.
+static int scan_nw(int ch64) { return ch64 <= 8 ? 1 : ch64 <= 16 ? 2 : 4; }
+
+static int scan_cht(int ch64) {
+  const int nw = scan_nw(ch64);
+  const int ch = (ch64 + nw - 1) / nw;
   int c = 1;
-  while (c < ch_max) c <<= 1;
+  while (c < ch) c <<= 1;
   return c;
 }
 
 size_t scan_lds_bytes(int ch_max) {
-  const int c = scan_cht(ch_max);
-  size_t b = sizeof(Shared);
-  if (c >= 8) b += sizeof(double) * (size_t)c * 4 * 64;
-  if (c >= 32) b += sizeof(double) * (size_t)(c + 1) * 4 * 64;
+  const int c = scan_cht(ch_max), nt = 64 * scan_nw(ch_max);
+  size_t b = sizeof(Shared) + (sizeof(cd) * 4 + sizeof(double) * 5) * (nt / 64);
+  if (c >= 8) b += sizeof(double) * (size_t)c * 4 * nt;
   return b;
 }
 
 hipError_t prepare_grad_scan(int ch_max) {
-  // static LDS only; the instances exist up to 32 levels per lane
-  return (ch_max >= 1 && scan_cht(ch_max) <= kScanMaxChunk) ? hipSuccess : hipErrorInvalidValue;
+  // static LDS only; every depth up to kMaxDeepLayers has an instance
+  return (ch_max >= 1 && ch_max <= kScanMaxChunk) ? hipSuccess : hipErrorInvalidValue;
 }
 
-template <int CHT>
+template <int CHT, int NW>
 static void launch_scan_cht(bool res, const KernelArgs& a, int n_wu, hipStream_t st) {
   if (res)
-    hipLaunchKernelGGL((k_loglik_grad_scan<CHT, true>), dim3(n_wu), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_loglik_grad_scan<CHT, NW, true>), dim3(n_wu), dim3(64 * NW), 0, st, a);
   else
-    hipLaunchKernelGGL((k_loglik_grad_scan<CHT, false>), dim3(n_wu), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_loglik_grad_scan<CHT, NW, false>), dim3(n_wu), dim3(64 * NW), 0, st,
+                       a);
 }
 
 hipError_t launch_grad_scan(bool res, int ch_max, const KernelArgs& a, int n_wu, hipStream_t st) {
   if (n_wu <= 0) return hipSuccess;
-  switch (scan_cht(ch_max)) {
-    case 1: launch_scan_cht<1>(res, a, n_wu, st); break;
-    case 2: launch_scan_cht<2>(res, a, n_wu, st); break;
-    case 4: launch_scan_cht<4>(res, a, n_wu, st); break;
-    case 8: launch_scan_cht<8>(res, a, n_wu, st); break;
-    case 16: launch_scan_cht<16>(res, a, n_wu, st); break;
-    case 32: launch_scan_cht<32>(res, a, n_wu, st); break;
+  if (ch_max < 1 || ch_max > kScanMaxChunk) return hipErrorInvalidValue;
+  switch (scan_nw(ch_max) * 100 + scan_cht(ch_max)) {
+    case 101: launch_scan_cht<1, 1>(res, a, n_wu, st); break;
+    case 102: launch_scan_cht<2, 1>(res, a, n_wu, st); break;
+    case 104: launch_scan_cht<4, 1>(res, a, n_wu, st); break;
+    case 108: launch_scan_cht<8, 1>(res, a, n_wu, st); break;
+    case 208: launch_scan_cht<8, 2>(res, a, n_wu, st); break;
+    case 408: launch_scan_cht<8, 4>(res, a, n_wu, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -81,6 +81,21 @@ def test_deep_items_match_oracle(nr, orc, depths):
     _check_items(nr, orc, batch, nr.Problem.from_batch(batch))
 
 
+# 600 slabs: two waves per data point; 1500 slabs: four; with a shallower
+# deep item in the same plan, each class in a launch of its own
+@pytest.mark.parametrize("depths", [[600], [45, 1500], [1100, 700, 300]])
+def test_multi_wave_points_match_oracle(nr, orc, depths):
+    rng = np.random.default_rng(860 + depths[0])
+    batch = _batch(rng, depths, nq=3, dqq=0.0)
+    _check_items(nr, orc, batch, nr.Problem.from_batch(batch))
+
+
+def test_multi_wave_smeared_with_resolution_gradient(nr, orc):
+    rng = np.random.default_rng(870)
+    batch = _batch(rng, [600], nq=1, dqq=0.04, extra_shallow=1)
+    _check_items(nr, orc, batch, nr.Problem.from_batch(batch), with_res=True)
+
+
 def test_deep_smeared_with_resolution_gradient_and_shallow_items(nr, orc):
     rng = np.random.default_rng(820)
     batch = _batch(rng, [45, 90], nq=5, dqq=0.04, extra_shallow=3)
