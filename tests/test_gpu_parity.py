@@ -28,8 +28,8 @@ def nr(torch_cuda):
     return nr
 
 
-def _run_all(nr, batch):
-    prob = nr.Problem.from_batch(batch)
+def _run_all(nr, batch, options=None):
+    prob = nr.Problem.from_batch(batch, options=options)
     Rhat = prob.reflectivity().cpu().numpy()
     ll = prob.loglik().cpu().numpy()
     llg, g_rows, g_inst = prob.loglik_grad()
@@ -95,16 +95,19 @@ def test_empty_dataset_items(nr):
     assert np.all(g_rows == 0.0) and np.all(g_inst == 0.0)
 
 
-def test_batched_workload_full_size_sampled(nr, orc):
-    """4096 draws x 10 layers x 400 Q, 17-node smearing, at full size; items
-    sampled across the batch are checked against the oracle."""
-    from paper_2509_06924_amd import inputs
+def test_batched_workload_full_size_sampled(nr, orc, tmp_path):
+    """4096 draws x 10 layers x 400 Q, 17-node smearing, at full size, with the
+    default schedule and with the one the autotuner picks (the benchmark's);
+    items sampled across the batch are checked against the oracle."""
+    from paper_2509_06924_amd import autotune, inputs
     batch = inputs.c2_batched()
-    prob, Rhat, ll, llg, g_rows, g_inst, st = _run_all(nr, batch)
-    assert np.all(st == 0)
-    assert np.all(np.isfinite(ll)) and np.all(np.isfinite(g_rows))
-    _check_items(orc, batch, [0, 1, 1234, 2047, 4095], Rhat, ll, llg, g_rows, g_inst,
-                 prob.out_off)
+    tuned = autotune.tune(batch, cache=str(tmp_path / "tune.json"), reps=3)
+    for options in (None, tuned):
+        prob, Rhat, ll, llg, g_rows, g_inst, st = _run_all(nr, batch, options)
+        assert np.all(st == 0)
+        assert np.all(np.isfinite(ll)) and np.all(np.isfinite(g_rows))
+        _check_items(orc, batch, [0, 1, 1234, 2047, 4095], Rhat, ll, llg, g_rows, g_inst,
+                     prob.out_off)
 
 
 def test_deterministic(nr, torch_cuda):
