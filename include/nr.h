@@ -62,8 +62,9 @@ extern "C" {
 #define NR_MAX_LAYERS 40
 /* Items deeper than NR_MAX_LAYERS (up to NR_MAX_DEEP_LAYERS, e.g. microsliced
  * SLD profiles) are accepted: their value kernels are the same; their gradient
- * uses the parallel-in-layers scan (layer product split across the 64 lanes
- * of a wave, one wave per data point), computed in FP64 in both precisions. */
+ * uses the parallel-in-layers scan (layer product split across the lanes of
+ * one, two or four waves per data point, at most 8 levels per lane), computed
+ * in FP64 in both precisions. */
 #define NR_MAX_DEEP_LAYERS 2047
 /* Number of quadrature nodes per data point when dq_over_q > 0. */
 #define NR_SMEAR_NODES 17
