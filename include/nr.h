@@ -169,7 +169,14 @@ nr_status nr_plan_create(const nr_batch_desc* desc, nr_plan** plan_out);
  *       NR_TAILS_SPLIT  for a smeared item, with the lanes split over 2 to 4
  *                       groups of smearing nodes (lane = node group x point;
  *                       12 to 32 points).
- *     Other tails follow pack_tails.  Default: both bits.
+ *     Other tails follow pack_tails.  A third bit serves small problems:
+ *       NR_SPLIT_SMALL  when the gradient's full units (64 points each) are
+ *                       fewer than one round of the device (two waves per
+ *                       SIMD), every point group of a smeared item of at most
+ *                       NR_MAX_LAYERS layers is split the same way, over
+ *                       G = min(17, round / units) node groups, so that a
+ *                       single fit spreads over many waves.
+ *     Default: all three bits.
  *   side_stream: 1 (default) runs every second full-unit launch of the
  *     gradient (one launch per layer-count bucket) and its tail and split
  *     launches that hold at most one round of the device (two waves per
@@ -178,12 +185,14 @@ nr_status nr_plan_create(const nr_batch_desc* desc, nr_plan** plan_out);
  *     after the per-layer constants and joined back before the reduction:
  *     small launches run beside the full-unit launches instead of leaving
  *     most of the device idle after them, and consecutive buckets overlap;
- *     0 keeps every launch on the caller's stream.  The fork and join are event waits, so
- *     calls stay ordered on the caller's stream and can be captured into a
- *     HIP graph (the side stream joins the capture).  Calls on one plan from
- *     several host threads are serialised around the fork and join. */
+ *     0 keeps every launch on the caller's stream.  The fork and join are
+ *     event waits, so calls stay ordered on the caller's stream and can be
+ *     captured into a HIP graph (the side stream joins the capture).  Calls
+ *     on one plan from several host threads are serialised around the fork
+ *     and join. */
 #define NR_TAILS_LONE 1
 #define NR_TAILS_SPLIT 2
+#define NR_SPLIT_SMALL 4
 #define NR_NUM_BUCKETS 16
 #define NR_VARIANT_AUTO 0
 #define NR_VARIANT_STORE 1
@@ -197,7 +206,8 @@ typedef struct nr_plan_options {
 } nr_plan_options;
 
 /* Fills *opts with the defaults (all NR_VARIANT_AUTO, xcd_run 8,
- * pack_tails 1, split_tails NR_TAILS_LONE | NR_TAILS_SPLIT, side_stream 1).
+ * pack_tails 1, split_tails NR_TAILS_LONE | NR_TAILS_SPLIT | NR_SPLIT_SMALL,
+ * side_stream 1).
  * NR_EINVAL for NULL. */
 nr_status nr_plan_options_default(nr_plan_options* opts);
 

@@ -18,7 +18,7 @@ NR_NUM_BUCKETS = 16
 NR_VARIANT_AUTO, NR_VARIANT_STORE, NR_VARIANT_RECOMPUTE = 0, 1, 2
 NR_TF_FIXED, NR_TF_AFFINE, NR_TF_LOG, NR_TF_LOGIT = 0, 1, 2, 3
 NR_HMC_ADAPT_MASS, NR_HMC_ADAPT_STEP = 1, 2
-NR_TAILS_LONE, NR_TAILS_SPLIT = 1, 2
+NR_TAILS_LONE, NR_TAILS_SPLIT, NR_SPLIT_SMALL = 1, 2, 4
 NR_HMC_MASS_WINDOW_END, NR_HMC_STEP_RESTART, NR_HMC_STEP_FINAL = 1, 2, 4
 
 # every symbol include/nr.h declares

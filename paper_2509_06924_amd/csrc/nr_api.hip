@@ -619,7 +619,7 @@ nr_status nr_plan_options_default(nr_plan_options* o) {
   for (int k = 0; k < NR_NUM_BUCKETS; ++k) o->grad_variant[k] = NR_VARIANT_AUTO;
   o->xcd_run = 8;
   o->pack_tails = 1;
-  o->split_tails = NR_TAILS_LONE | NR_TAILS_SPLIT;
+  o->split_tails = NR_TAILS_LONE | NR_TAILS_SPLIT | NR_SPLIT_SMALL;
   o->side_stream = 1;
   return NR_OK;
 }
@@ -644,7 +644,7 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
   nr_plan_options_default(&o);
   if (opts) o = *opts;
   if (o.xcd_run < 1 || o.xcd_run > 64 || (o.pack_tails != 0 && o.pack_tails != 1) ||
-      (o.split_tails & ~(NR_TAILS_LONE | NR_TAILS_SPLIT)) ||
+      (o.split_tails & ~(NR_TAILS_LONE | NR_TAILS_SPLIT | NR_SPLIT_SMALL)) ||
       (o.side_stream != 0 && o.side_stream != 1))
     return NR_EINVAL;
   bool bucket_store[kNumBuckets];
@@ -711,6 +711,27 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
   std::vector<int64_t> ll_first(nI), ll_offs, gr_first(nI), gr_offs;
   std::vector<int32_t> ll_count(nI), gr_count(nI);
   int64_t rec_ll = 0, rec_gr = 0;
+  // Small problems (NR_SPLIT_SMALL): fewer full units than one round of the
+  // device leave most of it idle for the whole call, each wave running all 17
+  // nodes of its points; splitting the nodes of every point group over G
+  // lanes gives G times the waves, each running 17 / G nodes.
+  int small_G = 1;
+  if (p->opts.split_tails & NR_SPLIT_SMALL) {
+    int64_t units = 0;
+    for (int b = 0; b < nI; ++b) {
+      const int s = p->dataset_of_item[b];
+      const int N = (int)(p->row_off[b + 1] - p->row_off[b]) - 2;
+      if (bucket_of(N) != kDeepBucket)
+        units += (p->q_off[s + 1] - p->q_off[s] + kWuPoints - 1) / kWuPoints;
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) !=
+        hipSuccess)
+      cus = 0;
+    const int64_t round = 2 * 4 * (int64_t)cus;
+    if (units > 0 && units < round)
+      small_G = (int)std::min<int64_t>(kSmearNodes, round / units);
+  }
   for (int b = 0; b < nI; ++b) {
     const int s = p->dataset_of_item[b];
     const int64_t nq = p->q_off[s + 1] - p->q_off[s];
@@ -741,6 +762,23 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
         gr_offs.push_back(rec_gr);
         rec_gr += rsz;
       }
+      continue;
+    }
+    if (K > 1 && small_G >= 2) {
+      // every point group split over small_G node groups (lane = g npts + p)
+      const int npts = kWuPoints / small_G;
+      gr_first[b] = (int64_t)gr_offs.size();
+      int32_t cnt = 0;
+      for (int64_t p0 = 0; p0 < nq; p0 += npts) {
+        const int np = (int)std::min<int64_t>(npts, nq - p0);
+        Wu u{b, (int32_t)p0, rec_gr, (double)np * K * (N + 1)};
+        u.split = np | (small_G << 16);
+        split_units[bk].push_back(u);
+        gr_offs.push_back(rec_gr);
+        rec_gr += rsz;
+        ++cnt;
+      }
+      gr_count[b] = cnt;
       continue;
     }
     const int nfull = (int)(nq / kWuPoints);

@@ -177,7 +177,7 @@ extern "C" nr_status nr_autotune(const nr_batch_desc* d, const nr_values* v, int
     o.pack_tails = 1 - o.pack_tails;
     if ((st = consider(o)) != NR_OK) return st;
   }
-  for (int bit : {NR_TAILS_LONE, NR_TAILS_SPLIT}) {
+  for (int bit : {NR_TAILS_LONE, NR_TAILS_SPLIT, NR_SPLIT_SMALL}) {
     nr_plan_options o = best;
     o.split_tails ^= bit;
     if ((st = consider(o)) != NR_OK) return st;

@@ -149,7 +149,7 @@ def test_plan_options_defaults_and_dict():
     from paper_2509_06924_amd import plan_options
     o = plan_options()
     assert list(o.grad_variant) == [n.NR_VARIANT_AUTO] * n.NR_NUM_BUCKETS
-    assert o.xcd_run == 8 and o.pack_tails == 1 and o.split_tails == 3 and o.side_stream == 1
+    assert o.xcd_run == 8 and o.pack_tails == 1 and o.split_tails == 7 and o.side_stream == 1
     o = plan_options({"grad_variant": {"10": n.NR_VARIANT_RECOMPUTE}, "xcd_run": 4,
                       "pack_tails": 0, "side_stream": 0})
     k10 = [L.nr_bucket_lmax(k) for k in range(n.NR_NUM_BUCKETS)].index(10)
@@ -173,7 +173,7 @@ def test_invalid_plan_options_rejected(case):
     elif case == "pack_two":
         o.pack_tails = 2
     elif case == "split_two":
-        o.split_tails = 4
+        o.split_tails = 8
     elif case == "side_two":
         o.side_stream = 2
     elif case == "side_negative":

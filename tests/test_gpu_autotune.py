@@ -55,6 +55,8 @@ def _check_against_oracle(nr, orc, batch, options):
      "grad_variant": {str(k): 2 for k in (1, 2, 4, 6, 8, 10)}},
     {"side_stream": 0},
     {"side_stream": 0, "split_tails": 0, "pack_tails": 0},
+    {"split_tails": 3},   # no small-plan split
+    {"split_tails": 4},   # the small-plan split only
 ])
 def test_schedules_match_oracle(nr, orc, options):
     _check_against_oracle(nr, orc, _batch(501), options)

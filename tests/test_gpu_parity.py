@@ -110,6 +110,18 @@ def test_batched_workload_full_size_sampled(nr, orc, tmp_path):
                      prob.out_off)
 
 
+@pytest.mark.parametrize("n_items", [1, 5, 40])
+def test_small_smeared_plans(nr, orc, n_items):
+    """Draws of the 10-layer, 400-point, 5 % dQ/Q workload in plans small
+    enough that every point group is split over node groups (17, 17 and 6
+    groups for 1, 5 and 40 items); the last draw against the oracle."""
+    from paper_2509_06924_amd import inputs
+    batch = inputs.c2_batched(n_items=n_items)
+    prob, Rhat, ll, llg, g_rows, g_inst, st = _run_all(nr, batch)
+    assert np.all(st == 0)
+    _check_items(orc, batch, [n_items - 1], Rhat, ll, llg, g_rows, g_inst, prob.out_off)
+
+
 def test_deterministic(nr, torch_cuda):
     from paper_2509_06924_amd import inputs
     rng = np.random.default_rng(9)
