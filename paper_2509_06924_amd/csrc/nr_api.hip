@@ -310,7 +310,7 @@ nr_status run_launches(const nr_plan* p, int op, KernelArgs a, hipStream_t st, b
     const int mode = L.tail ? kModeTail : L.split ? kModeSplit : kModeFull;
     const hipStream_t ls = (fork && L.side) ? p->side : st;
     if (!grad)
-      launch_err = launch_forward(p->precision, op, a, L.n_wu, ls);
+      launch_err = launch_forward(p->precision, op, L.split, a, L.n_wu, ls);
     else if (L.bucket == kDeepBucket)
       launch_err = launch_grad_scan(res, L.scan_ch, a, L.n_wu, ls);
     else
@@ -705,7 +705,7 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
   constexpr int kDeepClasses = 3;
   std::vector<std::vector<Wu>> fwd_units(kNumBuckets + 1);
   std::vector<std::vector<Wu>> grad_units(kNumBuckets + kDeepClasses);
-  std::vector<std::vector<Wu>> split_units(kNumBuckets);
+  std::vector<std::vector<Wu>> split_units(kNumBuckets), fwd_split_units(kNumBuckets);
   int scan_ch[kDeepClasses] = {0, 0, 0};
   std::map<std::pair<int, int>, std::vector<Tail>> tails;  // (depth, nodes)
   std::vector<int64_t> ll_first(nI), ll_offs, gr_first(nI), gr_offs;
@@ -715,14 +715,17 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
   // device leave most of it idle for the whole call, each wave running all 17
   // nodes of its points; splitting the nodes of every point group over G
   // lanes gives G times the waves, each running 17 / G nodes.
-  int small_G = 1;
+  // The value kernels (nr_loglik, nr_reflectivity) take the same split, with
+  // their own unit count (deep items included: they have no scan form).
+  int small_G = 1, small_G_fwd = 1;
   if (p->opts.split_tails & NR_SPLIT_SMALL) {
-    int64_t units = 0;
+    int64_t units = 0, units_fwd = 0;
     for (int b = 0; b < nI; ++b) {
       const int s = p->dataset_of_item[b];
       const int N = (int)(p->row_off[b + 1] - p->row_off[b]) - 2;
-      if (bucket_of(N) != kDeepBucket)
-        units += (p->q_off[s + 1] - p->q_off[s] + kWuPoints - 1) / kWuPoints;
+      const int64_t u = (p->q_off[s + 1] - p->q_off[s] + kWuPoints - 1) / kWuPoints;
+      units_fwd += u;
+      if (bucket_of(N) != kDeepBucket) units += u;
     }
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) !=
@@ -731,6 +734,8 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
     const int64_t round = 2 * 4 * (int64_t)cus;
     if (units > 0 && units < round)
       small_G = (int)std::min<int64_t>(kSmearNodes, round / units);
+    if (units_fwd > 0 && units_fwd < round)
+      small_G_fwd = (int)std::min<int64_t>(kSmearNodes, round / units_fwd);
   }
   for (int b = 0; b < nI; ++b) {
     const int s = p->dataset_of_item[b];
@@ -740,14 +745,29 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
     const int bk = bucket_of(N);
     const int64_t rsz = 4 + 4 * (N + 2);
     p->out_off[b + 1] = p->out_off[b] + nq;
-    const int nwu = (int)((nq + kWuPoints - 1) / kWuPoints);
     ll_first[b] = (int64_t)ll_offs.size();
-    ll_count[b] = nwu;
-    for (int k = 0; k < nwu; ++k) {
-      const int p0 = k * kWuPoints;
-      const double pts = (double)std::min<int64_t>(kWuPoints, nq - p0);
-      fwd_units[bk].push_back({b, p0, rec_ll, pts * K * (N + 1)});
-      ll_offs.push_back(rec_ll++);
+    if (K > 1 && small_G_fwd >= 2) {
+      // value units split like the gradient's (lane = g npts + p)
+      const int npts = kWuPoints / small_G_fwd;
+      int32_t cnt = 0;
+      for (int64_t p0 = 0; p0 < nq; p0 += npts) {
+        const int np = (int)std::min<int64_t>(npts, nq - p0);
+        Wu u{b, (int32_t)p0, rec_ll, (double)np * K * (N + 1)};
+        u.split = np | (small_G_fwd << 16);
+        fwd_split_units[std::min(bk, kNumBuckets - 1)].push_back(u);
+        ll_offs.push_back(rec_ll++);
+        ++cnt;
+      }
+      ll_count[b] = cnt;
+    } else {
+      const int nwu = (int)((nq + kWuPoints - 1) / kWuPoints);
+      ll_count[b] = nwu;
+      for (int k = 0; k < nwu; ++k) {
+        const int p0 = k * kWuPoints;
+        const double pts = (double)std::min<int64_t>(kWuPoints, nq - p0);
+        fwd_units[bk].push_back({b, p0, rec_ll, pts * K * (N + 1)});
+        ll_offs.push_back(rec_ll++);
+      }
     }
     p->max_rows = std::max(p->max_rows, N + 2);
     if (bk == kDeepBucket) {
@@ -959,6 +979,7 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
     }
   };
   make_full(fwd_units, p->launches_fwd, false);
+  make_full(fwd_split_units, p->launches_fwd, true);
   make_full(grad_units, p->launches_grad, false);
   const size_t n_main = p->launches_grad.size();
   make_full(split_units, p->launches_grad, true);

@@ -115,7 +115,8 @@ struct ReduceArgs {
 hipError_t launch_item_consts(const int64_t* row_off, const double* layers, double* rec,
                               float* recf, int n_items, hipStream_t st);
 // precision: NR_F64 or NR_F32
-hipError_t launch_forward(int precision, int op, const KernelArgs& a, int n_wu, hipStream_t st);
+hipError_t launch_forward(int precision, int op, bool split, const KernelArgs& a, int n_wu,
+                          hipStream_t st);
 // store: the store variant (only for buckets within store_max_layers)
 // Forms of the gradient kernel: the recompute form, the store form (buckets up
 // to the precision's store limit), and the recompute form that also
@@ -127,7 +128,7 @@ enum GradForm { kFormRecompute = 0, kFormStore = 1, kFormRecomputeRes = 2 };
 enum WuMode { kModeFull = 0, kModeTail = 1, kModeSplit = 2 };
 hipError_t launch_grad(int precision, int bucket, int form, int mode, const KernelArgs& a,
                        int n_wu, hipStream_t st);
-hipError_t launch_forward_f32(int op, const KernelArgs& a, int n_wu, hipStream_t st);
+hipError_t launch_forward_f32(int op, bool split, const KernelArgs& a, int n_wu, hipStream_t st);
 hipError_t launch_grad_f32(int bucket, int form, int mode, const KernelArgs& a, int n_wu,
                            hipStream_t st);
 // Deep buckets (index >= kFirstDeepBucket): one object per (precision,

@@ -367,25 +367,54 @@ __device__ __forceinline__ void flag(int32_t* status, int item, uint32_t bits) {
 }
 
 // ---------------------------------------------------------------------------
-// R_hat per point (nr_reflectivity).
+// Smeared R of a forward unit's point.  SPLIT: the unit holds npts points of
+// one item and lane g npts + p evaluates point p on the nodes g, g + G, ...;
+// the point's G lanes then add their partial sums, so that every one of them
+// holds the point's smeared R (split_setup).
 // ---------------------------------------------------------------------------
-template <class P>
-__global__ __launch_bounds__(64) void k_reflectivity(KernelArgs a) {
-  __shared__ Shared s;
-  const int lane = threadIdx.x;
-  const int w = blockIdx.x;
-  const WuInfo u = wu_setup(a, w, lane);
-  stage_shared(s, lane, a.rule);
+template <class P, bool SPLIT>
+__device__ __forceinline__ double forward_point(const KernelArgs& a, const Shared& s,
+                                                const WuInfo& u, const SplitInfo& sp, int lane,
+                                                bool& badq) {
   const int K = u.smeared ? kSmearNodes : 1;
+  const int k0 = SPLIT ? (u.active ? sp.g : K) : 0;
+  const int kstep = SPLIT ? sp.G : 1;
   double Rsm = 0.0;
-  bool badq = !(u.Q > 0.0);
-  for (int k = 0; k < K; ++k) {
+  badq = !(u.Q > 0.0);
+  for (int k = k0; k < K; k += kstep) {
     const double q = (K == 1) ? u.Q : smear_at(u.Q, u.sig, ld(s.t[k]));
     badq |= !(q > 0.0);
     const double wk = (K == 1) ? 1.0 : ld(s.w[k]);
     Rsm += wk * node_reflectivity(s.tab, item_layers<P>(a, u.roff, u.N, k), u.N, q);
   }
-  if (u.active) {
+  if constexpr (SPLIT) {
+    double tot = 0.0;
+    int bq = 0;
+    for (int gg = 0; gg < sp.G; ++gg) {
+      const int src = gg * sp.npts + lane % sp.npts;
+      tot += __shfl(Rsm, src, 64);
+      bq |= __shfl(badq ? 1 : 0, src, 64);
+    }
+    Rsm = tot;
+    badq = bq != 0;
+  }
+  return Rsm;
+}
+
+// ---------------------------------------------------------------------------
+// R_hat per point (nr_reflectivity).
+// ---------------------------------------------------------------------------
+template <class P, bool SPLIT = false>
+__global__ __launch_bounds__(64) void k_reflectivity(KernelArgs a) {
+  __shared__ Shared s;
+  const int lane = threadIdx.x;
+  const int w = blockIdx.x;
+  SplitInfo sp{0, 1, 64};
+  const WuInfo u = SPLIT ? split_setup(a, w, lane, sp) : wu_setup(a, w, lane);
+  stage_shared(s, lane, a.rule);
+  bool badq = false;
+  const double Rsm = forward_point<P, SPLIT>(a, s, u, sp, lane, badq);
+  if (u.active && sp.g == 0) {
     double Rhat = a.scale[u.item] * Rsm + a.bkg[u.item];
     uint32_t bits = 0;
     if (badq) {
@@ -413,25 +442,19 @@ __device__ __forceinline__ double point_loglik(double Rhat, double Robs, double 
 // ---------------------------------------------------------------------------
 // logL partial per WU (nr_loglik): record = 1 double.
 // ---------------------------------------------------------------------------
-template <class P>
+template <class P, bool SPLIT = false>
 __global__ __launch_bounds__(64) void k_loglik(KernelArgs a) {
   __shared__ Shared s;
   const int lane = threadIdx.x;
   const int w = blockIdx.x;
-  const WuInfo u = wu_setup(a, w, lane);
+  SplitInfo sp{0, 1, 64};
+  const WuInfo u = SPLIT ? split_setup(a, w, lane, sp) : wu_setup(a, w, lane);
   stage_shared(s, lane, a.rule);
-  const int K = u.smeared ? kSmearNodes : 1;
-  double Rsm = 0.0;
-  bool badq = !(u.Q > 0.0);
-  for (int k = 0; k < K; ++k) {
-    const double q = (K == 1) ? u.Q : smear_at(u.Q, u.sig, ld(s.t[k]));
-    badq |= !(q > 0.0);
-    const double wk = (K == 1) ? 1.0 : ld(s.w[k]);
-    Rsm += wk * node_reflectivity(s.tab, item_layers<P>(a, u.roff, u.N, k), u.N, q);
-  }
+  bool badq = false;
+  const double Rsm = forward_point<P, SPLIT>(a, s, u, sp, lane, badq);
   double ll = 0.0;
   uint32_t bits = 0;
-  if (u.active) {
+  if (u.active && sp.g == 0) {
     const double Rhat = a.scale[u.item] * Rsm + a.bkg[u.item];
     ll = point_loglik(Rhat, a.r_obs[u.qoff + u.i], a.r_err[u.qoff + u.i], badq, bits);
   }
@@ -1032,12 +1055,19 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(K
 // nr_kernels_f32.hip).
 // ---------------------------------------------------------------------------
 template <class P>
-hipError_t launch_forward_p(int op, const KernelArgs& a, int n_wu, hipStream_t st) {
+hipError_t launch_forward_p(int op, bool split, const KernelArgs& a, int n_wu, hipStream_t st) {
   if (n_wu <= 0) return hipSuccess;
-  if (op == kOpReflectivity)
-    hipLaunchKernelGGL(k_reflectivity<P>, dim3(n_wu), dim3(64), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_loglik<P>, dim3(n_wu), dim3(64), 0, st, a);
+  if (op == kOpReflectivity) {
+    if (split)
+      hipLaunchKernelGGL((k_reflectivity<P, true>), dim3(n_wu), dim3(64), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_reflectivity<P, false>), dim3(n_wu), dim3(64), 0, st, a);
+  } else {
+    if (split)
+      hipLaunchKernelGGL((k_loglik<P, true>), dim3(n_wu), dim3(64), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_loglik<P, false>), dim3(n_wu), dim3(64), 0, st, a);
+  }
   return hipGetLastError();
 }
 

@@ -6,8 +6,8 @@ namespace nr {
 
 NR_DEFINE_GRAD_LAUNCHER(launch_grad_shallow, NR_BUCKETS_SHALLOW)
 
-hipError_t launch_forward_f32(int op, const KernelArgs& a, int n_wu, hipStream_t st) {
-  return launch_forward_p<F32>(op, a, n_wu, st);
+hipError_t launch_forward_f32(int op, bool split, const KernelArgs& a, int n_wu, hipStream_t st) {
+  return launch_forward_p<F32>(op, split, a, n_wu, st);
 }
 
 hipError_t launch_grad_f32(int bucket, int form, int mode, const KernelArgs& a, int n_wu,

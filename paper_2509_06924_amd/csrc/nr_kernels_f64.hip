@@ -143,9 +143,10 @@ hipError_t launch_item_consts(const int64_t* row_off, const double* layers, doub
   return hipGetLastError();
 }
 
-hipError_t launch_forward(int precision, int op, const KernelArgs& a, int n_wu, hipStream_t st) {
-  return precision == NR_F32 ? launch_forward_f32(op, a, n_wu, st)
-                             : launch_forward_p<F64>(op, a, n_wu, st);
+hipError_t launch_forward(int precision, int op, bool split, const KernelArgs& a, int n_wu,
+                          hipStream_t st) {
+  return precision == NR_F32 ? launch_forward_f32(op, split, a, n_wu, st)
+                             : launch_forward_p<F64>(op, split, a, n_wu, st);
 }
 
 hipError_t launch_grad(int precision, int bucket, int form, int mode, const KernelArgs& a,
