@@ -82,9 +82,13 @@ struct F32 {
   // layers; at 32-40 layers (516-836 B) they lost 6-27 %.
   static constexpr int min_waves(int lmax, bool) { return (lmax <= 28 && lmax != 16) ? 2 : 1; }
   // 1 KB per level; up to 28 layers the LDS of a kernel that may share the
-  // SIMD with a second wave stays within 20 KB
+  // SIMD with a second wave stays within 20 KB; up to 10 layers the kernel
+  // fits three waves per SIMD in registers, and 9 levels keep its LDS within
+  // 160 KB / 12 waves (at 11 levels only 11 waves fit a CU: 3-5 % slower)
   static constexpr int ef_levels(int lmax) {
-    return lmax <= 28 ? (lmax + 1 < 16 ? lmax + 1 : 16) : (lmax + 1 < 35 ? lmax + 1 : 35);
+    return lmax <= 10   ? (lmax + 1 < 9 ? lmax + 1 : 9)
+           : lmax <= 28 ? (lmax + 1 < 16 ? lmax + 1 : 16)
+                        : (lmax + 1 < 35 ? lmax + 1 : 35);
   }
   static constexpr bool checkpoint(int lmax) { return lmax == 18 || lmax == 20 || lmax >= 24; }
   // from 12 layers, at one or two waves per SIMD (12 layers 5 % faster, 14-28
