@@ -123,6 +123,10 @@ def make_workload(name):
         b = inputs.c5_vi()
         cfg = {"workload": "8192 VI samples x 20 layers x 1000 Q, 5% dQ/Q", "samples": 8192,
                "layers": 20}
+    elif name == "deep":
+        b = inputs.microsliced()
+        cfg = {"workload": "64 microsliced profiles x 1000 slabs x 200 Q, 5% dQ/Q (scan gradient)",
+               "items": 64, "layers": 1000, "q_points": 200}
     else:
         raise SystemExit(f"unknown workload {name}")
     return b, cfg

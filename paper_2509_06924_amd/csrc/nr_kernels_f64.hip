@@ -1,6 +1,8 @@
-// FP64 instantiation of the kernels (shallow buckets; the deep ones are in
-// nr_kernels_f64_deep.hip), the per-item constant prologue, the per-item
+// FP64 instantiation of the kernels (shallow buckets; the deeper ones are
+// compiled from nr_kernels_bucket.hip), the per-item constant prologue, the per-item
 // reductions, and the launch entry points of both precisions.
+#include <algorithm>
+
 #include "nr_kernels.hpp"
 
 namespace nr {
@@ -69,12 +71,17 @@ __global__ __launch_bounds__(256) void k_reduce_loglik(ReduceArgs a) {
   a.logL[b] = s;
 }
 
-// One wave per item: lanes sum record fields over the item's WUs, then turn
-// the sums into gradients of the row entries.
-__global__ __launch_bounds__(64) void k_reduce_grad(ReduceArgs a) {
+// One block per item of 64 x W threads (W from the plan's deepest item, so
+// that the thousands of fields of a deep item's records are spread over
+// many waves): threads sum record fields over the item's WUs, then turn the
+// sums into gradients of the row entries.
+__global__ __launch_bounds__(1024) void k_reduce_grad(ReduceArgs a) {
   extern __shared__ double fsum[];
+  __shared__ int64_t offs[64];
+  __shared__ double wpart[16];
   const int b = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wv = tid >> 6;
   const int64_t first = a.item_wu_first[b];
   const int cnt = a.item_wu_count[b];
   const int64_t roff = a.row_off[b];
@@ -82,16 +89,16 @@ __global__ __launch_bounds__(64) void k_reduce_grad(ReduceArgs a) {
   // records hold 4 + 4 NR doubles; the last is written by the resolution
   // form only
   const int nf = (a.g_res ? 4 : 3) + 4 * NR;
-  // The units' record offsets are staged 64 at a time (one load per lane),
-  // so the record loads of a chunk are independent of each other instead of
-  // each waiting for its offset; the sum runs over the units in order.
-  __shared__ int64_t offs[64];
+  // The units' record offsets are staged 64 at a time (one load per
+  // thread), so the record loads of a chunk are independent of each other
+  // instead of each waiting for its offset; the sum runs over the units in
+  // order.
   for (int k0 = 0; k0 < cnt; k0 += 64) {
     const int kc = min(64, cnt - k0);
     __syncthreads();  // the previous chunk's offsets are no longer read
-    if (lane < kc) offs[lane] = a.rec_of_wu[first + k0 + lane];
+    if (tid < kc) offs[tid] = a.rec_of_wu[first + k0 + tid];
     __syncthreads();
-    for (int f = lane; f < nf; f += 64) {
+    for (int f = tid; f < nf; f += nt) {
       double v = (k0 == 0) ? 0.0 : fsum[f];
 #pragma unroll 8
       for (int k = 0; k < kc; ++k) v += a.rec[offs[k] + f];
@@ -99,11 +106,11 @@ __global__ __launch_bounds__(64) void k_reduce_grad(ReduceArgs a) {
     }
   }
   if (cnt <= 0)
-    for (int f = lane; f < nf; f += 64) fsum[f] = 0.0;
+    for (int f = tid; f < nf; f += nt) fsum[f] = 0.0;
   __syncthreads();
   const double* rows = a.layers + 4 * roff;
   double* g = a.g_rows + 4 * roff;
-  for (int m = lane; m < NR; m += 64) {
+  for (int m = tid; m < NR; m += nt) {
     const double wr = fsum[3 + m], wi = fsum[3 + NR + m];
     const double dd = fsum[3 + 2 * NR + m], ss = fsum[3 + 3 * NR + m];
     double gd = 0.0, gre = 0.0, gim = 0.0, gsig = 0.0;
@@ -119,12 +126,17 @@ __global__ __launch_bounds__(64) void k_reduce_grad(ReduceArgs a) {
     g[4 * m + 2] = gim;
     g[4 * m + 3] = gsig;
   }
-  // fronting rho_re: the model depends on rho_re,m - rho_re,0 only
+  // fronting rho_re: the model depends on rho_re,m - rho_re,0 only; the
+  // waves' partial sums are added in wave order
   double part = 0.0;
-  for (int m = 1 + lane; m < NR; m += 64) part += fsum[3 + m];
+  for (int m = 1 + tid; m < NR; m += nt) part += fsum[3 + m];
   part = wave_sum(part);
-  if (lane == 0) {
-    g[1] = kFourPi * part;
+  if (lane == 0) wpart[wv] = part;
+  __syncthreads();
+  if (tid == 0) {
+    double tot = 0.0;
+    for (int v = 0; v < nt / 64; ++v) tot += wpart[v];
+    g[1] = kFourPi * tot;
     a.logL[b] = fsum[0];
     a.g_inst[2 * b + 0] = fsum[1];
     a.g_inst[2 * b + 1] = fsum[2];
@@ -180,7 +192,9 @@ hipError_t launch_reduce(int op, const ReduceArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_reduce_loglik, dim3((a.n_items + 255) / 256), dim3(256), 0, st, a);
   } else {
     const size_t shmem = sizeof(double) * (4 + 4 * (size_t)a.max_rows);
-    hipLaunchKernelGGL(k_reduce_grad, dim3(a.n_items), dim3(64), shmem, st, a);
+    // one wave per 64 rows of the deepest item, at most 16
+    const int waves = std::min(16, std::max(1, (a.max_rows + 63) / 64));
+    hipLaunchKernelGGL(k_reduce_grad, dim3(a.n_items), dim3(64 * waves), shmem, st, a);
   }
   return hipGetLastError();
 }
