@@ -544,6 +544,27 @@ def deep_stack_row(nr, reps=3):
             "forward_only_ms": dtf * 1e3, "layer_steps_per_step": ls}
 
 
+def resolution_row(nr, reps=10):
+    """The 4096-draw batch through nr_loglik_grad_res (the gradient plus
+    dlogL/d(dQ/Q) per draw, from dR/dq at every smearing node) beside the
+    plain gradient call on the same plan."""
+    import torch
+
+    from paper_2509_06924_amd import inputs
+    batch = inputs.c2_batched()
+    prob = nr.Problem.from_batch(batch, device="cuda:0")
+    out = prob.loglik_grad()
+    stream = torch.cuda.current_stream()
+    dt_res = _timed(lambda: prob.loglik_grad_res(stream=stream), reps)
+    dt = _timed(lambda: prob.loglik_grad(out=out, stream=stream), reps)
+    ls = batch.layer_steps()
+    return {"what": "4096 draws x 10 layers x 400 Q, 5% dQ/Q: logL + gradient + dlogL/d(dQ/Q) "
+                    "(nr_loglik_grad_res) beside logL + gradient (nr_loglik_grad), same plan",
+            "ms_per_step": dt_res * 1e3, "value": ls / dt_res, "unit": UNIT,
+            "frac_fp64_peak": FLOP_PER_LAYER_STEP * ls / dt_res / FP64_VALU_PEAK,
+            "plain_gradient_ms": dt * 1e3}
+
+
 def vi_mvn_row(nr, reps=5):
     """The full-rank Gaussian VI of the paper's co-fit study: 100 restarts x
     8 draws of a 12-layer stack over 300 Q, 5% dQ/Q, one Adam step each."""
@@ -625,7 +646,8 @@ def other_workloads(nr):
     return {"single_film": single_film_row(nr), "cofit": cofit_row(nr),
             "ragged_hmc_f64": ragged_hmc_row(nr, nr.NR_F64),
             "ragged_hmc_f32": ragged_hmc_row(nr, nr.NR_F32), "hmc_driver": hmc_driver_row(nr),
-            "vi": vi_row(nr), "vi_mvn": vi_mvn_row(nr), "deep_stack": deep_stack_row(nr)}
+            "vi": vi_row(nr), "vi_mvn": vi_mvn_row(nr), "deep_stack": deep_stack_row(nr),
+            "resolution_grad": resolution_row(nr)}
 
 
 def plain_unbatched_row(nr, batch, n_items=64):
