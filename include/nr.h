@@ -140,6 +140,15 @@ int32_t nr_version(void);
  * recorded on the calling thread.  Never returns NULL. */
 const char* nr_status_string(nr_status status);
 
+/* The resolution quadrature that every smeared evaluation uses (Sec. 3
+ * pointwise Gaussian smearing, Sec. 4.1 FWHM): fills HOST t[NR_SMEAR_NODES]
+ * with the node offsets in units of sigma_Q (3.5 times the 17-point
+ * Gauss-Legendre abscissae on [-1, 1], ascending; the nodes of point Q are
+ * Q + sigma_Q t_k, sigma_Q = FWHM / (2 sqrt(2 ln 2))) and w[NR_SMEAR_NODES]
+ * with the weights u_k exp(-t_k^2 / 2) normalised to sum 1.  Host only: no
+ * device is touched.  NR_EINVAL for NULL. */
+nr_status nr_smearing_rule(double* t, double* w);
+
 /* Builds a plan from the host batch description: validates it, builds the
  * work list (one unit = one item x up to 64 consecutive points, ordered by
  * decreasing cost) and uploads it to the current device.  Allocates device

@@ -99,14 +99,6 @@ def reflectivity(rows, q):
     return R
 
 
-def amplitude(rows, q):
-    r, L = _rows(rows)
-    q = _vec(q)
-    out = np.empty(2 * q.size)
-    _check(lib().orc_amplitude(_I(L), _p(r), _I(q.size), _p(q), _p(out)))
-    return out[0::2] + 1j * out[1::2]
-
-
 def reflectivity_parratt(rows, q):
     r, L = _rows(rows)
     q = _vec(q)

@@ -64,6 +64,11 @@
 //   gradient ............... Richardson FD; single-interface closed forms;
 //                            translation invariance in rho_re; split-layer
 //                            identities; periodicity in d.
+//   VJP of R_hat ........... the likelihood seed reproduces the logL
+//                            gradient; a one-hot seed equals Richardson
+//                            differences of the model curve and the
+//                            weighted node Jacobian; linear in the seed.
+//   batched entry .......... equal, bitwise, to the per-item calls.
 //  Every function below is pinned; none is "parity unpinned".
 //
 //  Build: g++ -O2 -std=c++17 -ffp-contract=off -fopenmp -shared -fPIC
@@ -618,18 +623,6 @@ int orc_reflectivity(int L, const double* rows, int nq, const double* q, double*
   if (L < 0 || nq < 0) return -1;
   std::vector<cplx> zr(rows, rows + (L + 2) * 4);
   for (int i = 0; i < nq; ++i) R[i] = reflectivity(L, zr.data(), q[i]).real();
-  return 0;
-}
-
-// Complex reflection amplitude r = M10/M00: out[2*i], out[2*i+1].
-int orc_amplitude(int L, const double* rows, int nq, const double* q, double* out) {
-  if (L < 0 || nq < 0) return -1;
-  std::vector<cplx> zr(rows, rows + (L + 2) * 4);
-  for (int i = 0; i < nq; ++i) {
-    cplx r = abeles_amplitude(L, zr.data(), q[i]);
-    out[2 * i] = r.real();
-    out[2 * i + 1] = r.imag();
-  }
   return 0;
 }
 

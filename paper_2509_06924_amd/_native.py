@@ -30,7 +30,8 @@ EXPORTS = ("nr_version", "nr_status_string", "nr_plan_create", "nr_plan_destroy"
            "nr_store_max_layers", "nr_plan_create_ex", "nr_reflectivity_vjp",
            "nr_loglik_grad_res", "nr_hmc_create", "nr_hmc_destroy", "nr_hmc_init",
            "nr_hmc_transition", "nr_hmc_graph_create", "nr_hmc_adapt", "nr_vi_mvn_create",
-           "nr_vi_mvn_destroy", "nr_vi_mvn_step", "nr_vi_mvn_graph_create", "nr_autotune")
+           "nr_vi_mvn_destroy", "nr_vi_mvn_step", "nr_vi_mvn_graph_create", "nr_autotune",
+           "nr_smearing_rule")
 
 
 class BatchDesc(ctypes.Structure):
@@ -220,8 +221,19 @@ def lib():
                                   ctypes.POINTER(PlanOptions), P, P]
         L.nr_tie_sum.restype = ctypes.c_int32
         L.nr_tie_sum.argtypes = [ctypes.c_int64, P, P, P, P, P]
+        L.nr_smearing_rule.restype = ctypes.c_int32
+        L.nr_smearing_rule.argtypes = [P, P]
         _lib = L
     return _lib
+
+
+def smearing_rule():
+    """The library's quadrature: node offsets t_k (units of sigma_Q) and
+    normalised weights w_k, as two lists of NR_SMEAR_NODES floats."""
+    t = (ctypes.c_double * NR_SMEAR_NODES)()
+    w = (ctypes.c_double * NR_SMEAR_NODES)()
+    check(lib().nr_smearing_rule(ctypes.cast(t, ctypes.c_void_p), ctypes.cast(w, ctypes.c_void_p)))
+    return list(t), list(w)
 
 
 def check(status):

@@ -614,6 +614,12 @@ const char* nr_status_string(nr_status s) {
   }
 }
 
+nr_status nr_smearing_rule(double* t, double* w) {
+  if (!t || !w) return NR_EINVAL;
+  smearing_rule(t, w);
+  return NR_OK;
+}
+
 nr_status nr_plan_options_default(nr_plan_options* o) {
   if (!o) return NR_EINVAL;
   for (int k = 0; k < NR_NUM_BUCKETS; ++k) o->grad_variant[k] = NR_VARIANT_AUTO;

@@ -221,3 +221,16 @@ def test_binding_shares_torchs_hip_runtime():
                        timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     assert r.stdout.split() == ["1", "True"], r.stdout
+
+
+def test_quadrature_rule_is_bitwise_the_oracles():
+    """The kernel side builds its 17-point rule with its own Newton iteration
+    on the host; node offsets and weights must be the oracle's doubles
+    exactly (the smearing step of the model, Sec. 3 / Sec. 4.1)."""
+    import oracle
+    n, L = _lib()
+    t, w = n.smearing_rule()
+    to, wo = oracle.smear_rule(0.05)
+    assert np.array_equal(np.array(t), to)
+    assert np.array_equal(np.array(w), wo)
+    assert L.nr_smearing_rule(None, None) == n.NR_EINVAL
