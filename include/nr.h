@@ -75,6 +75,8 @@ typedef int32_t nr_status;
 #define NR_EWORKSPACE 2 /* workspace missing or smaller than required */
 #define NR_EHIP 3       /* a HIP runtime call or kernel launch failed */
 #define NR_ENOMEM 4     /* plan creation could not allocate device memory */
+#define NR_ESCRATCH 5   /* nr_loglik_grad_noalloc: the plan needs more workspace than
+                         * NR_NOALLOC_SCRATCH_BYTES */
 
 /* Arithmetic precision of the bulk layer product (wavevector roots, interface
  * coefficients, phases, the 2x2 product and its adjoint).  In both, the
@@ -283,6 +285,24 @@ nr_status nr_loglik(const nr_plan* plan, const nr_values* v, double* logL,
 nr_status nr_loglik_grad(const nr_plan* plan, const nr_values* v, double* logL,
                          double* g_rows, double* g_inst, void* workspace,
                          size_t workspace_bytes, void* stream);
+
+/* nr_loglik_grad without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving or
+ * sampling loops, harnesses that forbid allocation).  The library keeps a
+ * fixed scratch array of NR_NOALLOC_SCRATCH_BYTES in device memory, one copy
+ * per GPU, reserved when the library is first used on that GPU and held
+ * until the process ends; the call uses it in place of the workspace and
+ * itself allocates and frees nothing.  Same plan, values, outputs, results
+ * and status bits as nr_loglik_grad (the same kernels on the same schedule).
+ * The plan's workspace (nr_workspace_size for NR_OP_LOGLIK_GRAD) must fit:
+ * otherwise NR_ESCRATCH, before anything is enqueued.  Nothing in the scratch
+ * needs to start at zero; it keeps the last call's contents.  Every call on
+ * one GPU shares that GPU's scratch, whatever its plan or stream: calls that
+ * may overlap on one GPU (other streams, other host threads) race and give
+ * wrong results; order them on one stream or use nr_loglik_grad. */
+#define NR_NOALLOC_SCRATCH_BYTES (256u << 20)
+nr_status nr_loglik_grad_noalloc(const nr_plan* plan, const nr_values* v, double* logL,
+                                 double* g_rows, double* g_inst, void* stream);
 
 /* nr_loglik_grad plus the derivative of logL with respect to the relative
  * resolution (Sec. 4.2: the smearing size inferred as a parameter):

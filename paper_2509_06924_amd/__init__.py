@@ -153,6 +153,12 @@ def nr_loglik_grad(plan, values, logL, g_rows, g_inst, workspace, stream=None):
                                      _dp(g_inst), _dp(workspace), nb, _stream(stream)))
 
 
+def nr_loglik_grad_noalloc(plan, values, logL, g_rows, g_inst, stream=None):
+    """nr_loglik_grad on the library's fixed per-GPU scratch (no workspace)."""
+    _n.check(_n.lib().nr_loglik_grad_noalloc(plan.handle, ctypes.byref(values), _dp(logL),
+                                             _dp(g_rows), _dp(g_inst), _stream(stream)))
+
+
 class Problem:
     """Datasets resident on the device plus a plan; parameters may be swapped
     per call (same structure)."""

@@ -7,7 +7,8 @@ import os
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libnr.so")
 
-NR_OK, NR_EINVAL, NR_EWORKSPACE, NR_EHIP, NR_ENOMEM = 0, 1, 2, 3, 4
+NR_OK, NR_EINVAL, NR_EWORKSPACE, NR_EHIP, NR_ENOMEM, NR_ESCRATCH = 0, 1, 2, 3, 4, 5
+NR_NOALLOC_SCRATCH_BYTES = 256 << 20
 NR_F64, NR_F32 = 0, 1
 NR_OP_REFLECTIVITY, NR_OP_LOGLIK, NR_OP_LOGLIK_GRAD = 0, 1, 2
 NR_ITEM_NONFINITE, NR_ITEM_BAD_Q, NR_ITEM_BAD_ERR, NR_ITEM_EDGE_SINGULAR = 1, 2, 4, 8
@@ -31,7 +32,7 @@ EXPORTS = ("nr_version", "nr_status_string", "nr_plan_create", "nr_plan_destroy"
            "nr_loglik_grad_res", "nr_hmc_create", "nr_hmc_destroy", "nr_hmc_init",
            "nr_hmc_transition", "nr_hmc_graph_create", "nr_hmc_adapt", "nr_vi_mvn_create",
            "nr_vi_mvn_destroy", "nr_vi_mvn_step", "nr_vi_mvn_graph_create", "nr_autotune",
-           "nr_smearing_rule")
+           "nr_smearing_rule", "nr_loglik_grad_noalloc")
 
 
 class BatchDesc(ctypes.Structure):
@@ -221,6 +222,8 @@ def lib():
                                   ctypes.POINTER(PlanOptions), P, P]
         L.nr_tie_sum.restype = ctypes.c_int32
         L.nr_tie_sum.argtypes = [ctypes.c_int64, P, P, P, P, P]
+        L.nr_loglik_grad_noalloc.restype = ctypes.c_int32
+        L.nr_loglik_grad_noalloc.argtypes = [P, ctypes.POINTER(Values), P, P, P, P]
         L.nr_smearing_rule.restype = ctypes.c_int32
         L.nr_smearing_rule.argtypes = [P, P]
         _lib = L

@@ -25,6 +25,30 @@ nr_status hip_fail(hipError_t e, const char* what) {
   return NR_EHIP;
 }
 
+// Workspace of nr_loglik_grad_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends.  Host code must not pass the array's
+// name to a kernel or a copy (on the host it is only a stand-in symbol): the
+// device address of each GPU's copy is looked up once, with that GPU
+// current, and kept in scratch_addr.  Every call on one GPU shares its copy.
+__device__ __align__(256) unsigned char scratch[NR_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// The device address of `dev`'s scratch copy (dev must be current).
+nr_status scratch_addr(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return NR_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "scratch symbol address");
+    g_scratch_addr[dev] = ptr;
+  }
+  *out = g_scratch_addr[dev];
+  return NR_OK;
+}
+
 // 17-point Gauss-Legendre rule on [-1, 1]: Newton iteration on P_17 from
 // Tricomi's asymptotic initial guesses, in long double, weights
 // 2 / ((1 - x^2) P'_17(x)^2).  Nodes ascending; the centre node is exactly 0.
@@ -609,6 +633,9 @@ const char* nr_status_string(nr_status s) {
       return g_last_hip_error.empty() ? "HIP error" : g_last_hip_error.c_str();
     case NR_ENOMEM:
       return "device allocation failed";
+    case NR_ESCRATCH:
+      return "the plan's workspace exceeds the fixed scratch of nr_loglik_grad_noalloc "
+             "(NR_NOALLOC_SCRATCH_BYTES); use nr_loglik_grad with a workspace";
     default:
       return "unknown status";
   }
@@ -1440,6 +1467,20 @@ nr_status nr_loglik_grad(const nr_plan* p, const nr_values* v, double* logL, dou
   if (!logL || !g_rows || !g_inst) return NR_EINVAL;
   const size_t need = sizeof(double) * op_doubles(p, NR_OP_LOGLIK_GRAD);
   if (need > 0 && (!ws || ws_bytes < need)) return NR_EWORKSPACE;
+  return enqueue_grad(p, v, logL, g_rows, g_inst, ws, (hipStream_t)stream, true);
+}
+
+nr_status nr_loglik_grad_noalloc(const nr_plan* p, const nr_values* v, double* logL,
+                                 double* g_rows, double* g_inst, void* stream) {
+  nr_status st = check_call(p, v, true);
+  if (st != NR_OK) return st;
+  if (p->n_items == 0) return NR_OK;
+  if (!logL || !g_rows || !g_inst) return NR_EINVAL;
+  const size_t need = sizeof(double) * op_doubles(p, NR_OP_LOGLIK_GRAD);
+  if (need > (size_t)NR_NOALLOC_SCRATCH_BYTES) return NR_ESCRATCH;
+  void* ws = nullptr;
+  st = scratch_addr(p->device, &ws);
+  if (st != NR_OK) return st;
   return enqueue_grad(p, v, logL, g_rows, g_inst, ws, (hipStream_t)stream, true);
 }
 
