@@ -223,22 +223,31 @@ def microsliced(n_items=64, L=1000, nq=200, dz=2.0, dq_over_q=0.05, seed_offset=
     rng = np.random.default_rng(SEED_BASE + seed_offset)
     Q = log_grid(0.005, 0.3, nq)
     Robs, err = synthetic_curve(Q, rng)
-    z = (np.arange(L) + 0.5) * dz
-    span = L * dz
     items = []
     for _ in range(n_items):
-        c1, c2 = rng.uniform(0.2, 0.4) * span, rng.uniform(0.6, 0.8) * span
-        w = rng.uniform(0.03, 0.08) * span
-        rows = np.zeros((L + 2, 4))
-        rows[1:L + 1, 0] = dz
-        rows[1:L + 1, 1] = (1.0e-6 + 3.0e-6 / (1 + np.exp(-(z - c1) / w))
-                            - 2.0e-6 / (1 + np.exp(-(z - c2) / w)))
-        rows[1:L + 1, 2] = 5e-8
-        rows[1:L + 1, 3] = 0.5
-        rows[L + 1] = [0.0, SI_SLD, 5e-8, 3.0]
+        rows = microsliced_stack(rng, L, dz)
         items.append((0, rows, float(rng.uniform(0.9, 1.1)), 1e-7))
     return _pack("microsliced", [(Q, Robs, err, dq_over_q)], items,
                  {"L": L, "dz": dz})
+
+
+def microsliced_stack(rng, L, dz=2.0):
+    """One microsliced profile: L slices of dz A sampling a smooth two-film
+    SLD curve (centres at 0.2-0.4 and 0.6-0.8 of the depth, widths 3-8 %)
+    on silicon, absorption 5e-8, slice roughness 0.5 A, backing roughness
+    3 A."""
+    z = (np.arange(L) + 0.5) * dz
+    span = L * dz
+    c1, c2 = rng.uniform(0.2, 0.4) * span, rng.uniform(0.6, 0.8) * span
+    w = rng.uniform(0.03, 0.08) * span
+    rows = np.zeros((L + 2, 4))
+    rows[1:L + 1, 0] = dz
+    rows[1:L + 1, 1] = (1.0e-6 + 3.0e-6 / (1 + np.exp(-(z - c1) / w))
+                        - 2.0e-6 / (1 + np.exp(-(z - c2) / w)))
+    rows[1:L + 1, 2] = 5e-8
+    rows[1:L + 1, 3] = 0.5
+    rows[L + 1] = [0.0, SI_SLD, 5e-8, 3.0]
+    return rows
 
 
 def random_batch(rng, n_items, L_choices, nq_choices, dqq_choices, n_datasets=None):

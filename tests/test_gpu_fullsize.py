@@ -61,8 +61,9 @@ def _first(cond):
 
 def test_ragged_16384_items_sampled(nr, orc):
     """16384 items, L 2..40, nQ 100..1000, dQ/Q 2-8 %: the deepest and the
-    shallowest bucket, a middle bucket of each wave class, and items whose
-    trailing partial group is a lone, a split and a packed tail unit."""
+    shallowest bucket, a middle bucket of each wave class, items whose
+    trailing partial group is a lone, a split and a packed tail unit, and a
+    deep item with close to 1000 points (15 full units and a tail)."""
     from paper_2509_06924_amd import inputs
     batch = inputs.c4_ragged()
     L = np.diff(batch.row_off) - 2
@@ -77,6 +78,8 @@ def test_ragged_16384_items_sampled(nr, orc):
         "lone tail": _first((L <= 10) & (tail >= 48) & small),
         "split tail": _first((L <= 10) & (tail >= 12) & (tail <= 32) & small),
         "packed deep tail": _first((L >= 29) & (tail > 0) & (tail < 48) & small),
+        # most of the batch's work sits in deep items with many points
+        "L>=36, nQ>=900": _first((L >= 36) & (nq >= 900)),
     }
     prob, Rhat, ll, llg, g_rows, g_inst, st = _run(nr, batch)
     _check_all_items(batch, ll, llg, g_rows, st)

@@ -92,3 +92,20 @@ def test_sliced_layer_gradient_identities(orc):
     # the backing and the top interface are shared
     assert abs(gn[n + 1, 1] - g1[2, 1]) <= 1e-8 * abs(g1[2, 1])
     assert abs(gn[1, 3] - g1[1, 3]) <= 1e-8 * abs(g1[1, 3])
+
+
+def test_deep_abeles_against_fifty_digit_parratt(orc):
+    """The FP64 Abeles product on microsliced profiles of 300..2047 slabs
+    against the 50-digit Parratt values of tests/golden/deep_parratt50.json
+    (written by make_deep_parratt50.py from oracle/mp_reference.py): the
+    rounding of a deep product stays within the 1e-10 parity tolerance."""
+    import json
+    import os
+
+    from paper_2509_06924_amd import inputs
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "deep_parratt50.json")
+    for c in json.load(open(path))["cases"]:
+        rows = inputs.microsliced_stack(np.random.default_rng(c["seed"]), c["L"], c["dz"])
+        R = orc.reflectivity(rows, np.array(c["q"]))
+        assert rel(R, np.array(c["R"])) < 2e-11, c["L"]

@@ -190,6 +190,27 @@ def test_fifty_digit_reference(orc):
         assert rel(orc.reflectivity(rows, q), ref) < 5e-13
 
 
+def test_high_precision_reference_module(orc):
+    """oracle/mp_reference.py (the 50-digit reference used for the deep-stack
+    fixtures): at one interface it is the Fresnel / Nevot-Croce closed form
+    at the same precision; on shallow stacks the FP64 Abeles oracle agrees
+    with it to rounding."""
+    from oracle import mp_reference
+    mpmath.mp.dps = 50
+    for rho1, im1, sig in [(2.07e-6, 0.0, 5.0), (6.35e-6, 3e-7, 8.0), (-0.56e-6, 0.0, 3.0)]:
+        rows = np.array([[0, 0.0, 0, 0], [0, rho1, im1, sig]], float)
+        for qi in (0.004, 0.011, 0.05, 0.2):
+            a = mp_reference.parratt_R(rows, qi)
+            b = _fresnel_nc_mp(qi, 0.0, rho1, im1, sig)
+            assert abs(a - b) <= mpmath.mpf("1e-40") * abs(b)
+    rng = np.random.default_rng(5)
+    q = np.geomspace(0.005, 0.3, 9)
+    for L in [1, 4, 12]:
+        rows = rand_stack(rng, L)
+        ref = np.array([float(mp_reference.parratt_R(rows, qi)) for qi in q])
+        assert rel(orc.reflectivity(rows, q), ref) < 5e-12
+
+
 # ------------------------------------------------------------ invariances ---
 
 def test_split_layer_invariance(orc):
