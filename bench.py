@@ -591,19 +591,21 @@ def cofit_row(nr, reps=10):
     batch = inputs.c3_cofit()
     prob = nr.Problem.from_batch(batch, device="cuda:0")
     rows = int(batch.row_off[1] - batch.row_off[0])
-    per_draw = rows * 4  # all row entries but the backing rho_re, plus the shared bkg
+    # the shared parameters of a draw: the 12 layers' d, rho_re, rho_im,
+    # sigma, the backing roughness and the background (50); the fronting, the
+    # backing SLDs (the contrasts) and the scale are fixed
+    per_draw = (rows - 2) * 4 + 2
     nre = batch.layers.size
     tie = -np.ones(nre + 2 * batch.n_items, np.int64)
     for b in range(batch.n_items):
         d = b // 3
         k = 0
-        for r in range(rows):
+        for r in range(1, rows - 1):
             for f in range(4):
-                if r == rows - 1 and f == 1:
-                    continue
                 tie[(batch.row_off[b] + r) * 4 + f] = d * per_draw + k
                 k += 1
-        tie[nre + 2 * b + 1] = d * per_draw + k
+        tie[(batch.row_off[b] + rows - 1) * 4 + 3] = d * per_draw + k
+        tie[nre + 2 * b + 1] = d * per_draw + k + 1
     first, src = nr.tie_map_to_csr(tie, (batch.n_items // 3) * per_draw)
     first_t = torch.as_tensor(first, device="cuda:0")
     src_t = torch.as_tensor(src, device="cuda:0")

@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define NR_VERSION 1
+#define NR_VERSION 2
 /* Largest number of finite layers one item may have. */
 #define NR_MAX_LAYERS 40
 /* Items deeper than NR_MAX_LAYERS (up to NR_MAX_DEEP_LAYERS, e.g. microsliced
@@ -200,7 +200,14 @@ nr_status nr_plan_create(const nr_batch_desc* desc, nr_plan** plan_out);
  *     event waits, so calls stay ordered on the caller's stream and can be
  *     captured into a HIP graph (the side stream joins the capture).  Calls
  *     on one plan from several host threads are serialised around the fork
- *     and join. */
+ *     and join.
+ *   node_groups: the (sample, Q) tiling of the gradient's work units.  0
+ *     (default) follows the rules above (64 points per wave, each lane
+ *     running all 17 nodes of its point, except the split units); 2..17 puts
+ *     every point group of a smeared item of at most NR_MAX_LAYERS layers
+ *     into split units of G = node_groups node groups and 64 / G points per
+ *     wave (lane = node group x point) whatever the plan's size.  The value
+ *     calls are not affected. */
 #define NR_TAILS_LONE 1
 #define NR_TAILS_SPLIT 2
 #define NR_SPLIT_SMALL 4
@@ -214,11 +221,12 @@ typedef struct nr_plan_options {
   int32_t pack_tails;
   int32_t split_tails;
   int32_t side_stream;
+  int32_t node_groups;
 } nr_plan_options;
 
 /* Fills *opts with the defaults (all NR_VARIANT_AUTO, xcd_run 8,
  * pack_tails 1, split_tails NR_TAILS_LONE | NR_TAILS_SPLIT | NR_SPLIT_SMALL,
- * side_stream 1).
+ * side_stream 1, node_groups 0).
  * NR_EINVAL for NULL. */
 nr_status nr_plan_options_default(nr_plan_options* opts);
 

@@ -62,6 +62,8 @@ def plan_options(options=None):
         o.split_tails = int(options["split_tails"])
     if "side_stream" in options:
         o.side_stream = int(options["side_stream"])
+    if "node_groups" in options:
+        o.node_groups = int(options["node_groups"])
     return o
 
 
@@ -72,7 +74,7 @@ class Plan:
                  options=None):
         """options: None (defaults) or a dict with any of grad_variant (list of
         NR_NUM_BUCKETS ints or {bucket_lmax: variant}), xcd_run, pack_tails,
-        split_tails, side_stream."""
+        split_tails, side_stream, node_groups."""
         self.q_off = np.ascontiguousarray(q_off, np.int64)
         self.dq_over_q = np.ascontiguousarray(dq_over_q, np.float64)
         self.dataset_of_item = np.ascontiguousarray(dataset_of_item, np.int32)

@@ -54,6 +54,7 @@ class PlanOptions(ctypes.Structure):
         ("pack_tails", ctypes.c_int32),
         ("split_tails", ctypes.c_int32),
         ("side_stream", ctypes.c_int32),
+        ("node_groups", ctypes.c_int32),
     ]
 
 

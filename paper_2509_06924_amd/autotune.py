@@ -85,7 +85,8 @@ def options_to_dict(o):
     gv = {str(lm[k]): int(o.grad_variant[k]) for k in range(_n.NR_NUM_BUCKETS)
           if o.grad_variant[k] != _n.NR_VARIANT_AUTO}
     return {"grad_variant": gv, "xcd_run": int(o.xcd_run), "pack_tails": int(o.pack_tails),
-            "split_tails": int(o.split_tails), "side_stream": int(o.side_stream)}
+            "split_tails": int(o.split_tails), "side_stream": int(o.side_stream),
+            "node_groups": int(o.node_groups)}
 
 
 def tune(batch, precision=_n.NR_F64, device="cuda", cache=None, reps=7, verbose=False,

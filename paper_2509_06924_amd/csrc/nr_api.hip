@@ -654,6 +654,7 @@ nr_status nr_plan_options_default(nr_plan_options* o) {
   o->pack_tails = 1;
   o->split_tails = NR_TAILS_LONE | NR_TAILS_SPLIT | NR_SPLIT_SMALL;
   o->side_stream = 1;
+  o->node_groups = 0;
   return NR_OK;
 }
 
@@ -678,7 +679,8 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
   if (opts) o = *opts;
   if (o.xcd_run < 1 || o.xcd_run > 64 || (o.pack_tails != 0 && o.pack_tails != 1) ||
       (o.split_tails & ~(NR_TAILS_LONE | NR_TAILS_SPLIT | NR_SPLIT_SMALL)) ||
-      (o.side_stream != 0 && o.side_stream != 1))
+      (o.side_stream != 0 && o.side_stream != 1) ||
+      !(o.node_groups == 0 || (o.node_groups >= 2 && o.node_groups <= kSmearNodes)))
     return NR_EINVAL;
   bool bucket_store[kNumBuckets];
   for (int k = 0; k < kNumBuckets; ++k) {
@@ -770,6 +772,8 @@ nr_status nr_plan_create_ex(const nr_batch_desc* d, const nr_plan_options* opts,
     if (units_fwd > 0 && units_fwd < round)
       small_G_fwd = (int)std::min<int64_t>(kSmearNodes, round / units_fwd);
   }
+  // a tiling given by the caller: every point group split over node_groups
+  if (p->opts.node_groups >= 2) small_G = p->opts.node_groups;
   for (int b = 0; b < nI; ++b) {
     const int s = p->dataset_of_item[b];
     const int64_t nq = p->q_off[s + 1] - p->q_off[s];

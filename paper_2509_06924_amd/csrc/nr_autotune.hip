@@ -17,6 +17,7 @@ constexpr double kMinGain = 0.03;     // a candidate must be this much faster
 constexpr double kWarmupSeconds = 0.3;
 constexpr int kConfirmRounds = 3;
 constexpr int kXcdRuns[] = {1, 4, 8, 16, 32};
+constexpr int kNodeGroups[] = {2, 4, 8, 17};
 
 struct Buffers {
   void* ws = nullptr;
@@ -95,7 +96,8 @@ bool same(const nr_plan_options& x, const nr_plan_options& y) {
   for (int k = 0; k < NR_NUM_BUCKETS; ++k)
     if (x.grad_variant[k] != y.grad_variant[k]) return false;
   return x.xcd_run == y.xcd_run && x.pack_tails == y.pack_tails &&
-         x.split_tails == y.split_tails && x.side_stream == y.side_stream;
+         x.split_tails == y.split_tails && x.side_stream == y.side_stream &&
+         x.node_groups == y.node_groups;
 }
 
 }  // namespace
@@ -132,6 +134,9 @@ extern "C" nr_status nr_autotune(const nr_batch_desc* d, const nr_values* v, int
     } while (std::chrono::steady_clock::now() < t_end);
   }
 
+  // any smeared dataset in use (the node-group tilings apply to them)
+  bool smeared = false;
+  for (int i = 0; i < d->n_items; ++i) smeared |= d->dq_over_q[d->dataset_of_item[i]] > 0.0;
   // the buckets present that have both forms
   std::set<int> used;
   const int smax = nr_store_max_layers(d->precision);
@@ -187,6 +192,14 @@ extern "C" nr_status nr_autotune(const nr_batch_desc* d, const nr_values* v, int
     o.side_stream = 1 - o.side_stream;
     if ((st = consider(o)) != NR_OK) return st;
   }
+  // the (sample, Q) tiling: node groups per point (64 / G points per wave)
+  if (smeared)
+    for (int g : kNodeGroups)
+      if (g != best.node_groups) {
+        nr_plan_options o = best;
+        o.node_groups = g;
+        if ((st = consider(o)) != NR_OK) return st;
+      }
 
   // confirm against the defaults, interleaved so that drift cancels
   if (!same(best, def)) {

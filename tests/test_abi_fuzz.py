@@ -135,7 +135,8 @@ def test_corrupted_descriptions_are_rejected(b, what, pick):
 
 
 OPTION_CORRUPTIONS = ["xcd_run_low", "xcd_run_high", "pack_tails", "split_tails", "side_stream",
-                      "variant_unknown", "store_too_deep"]
+                      "variant_unknown", "store_too_deep", "node_groups_one", "node_groups_high",
+                      "node_groups_negative"]
 
 
 @SETTINGS
@@ -158,6 +159,12 @@ def test_corrupted_options_are_rejected(b, what, pick):
         o.side_stream = -1 - pick % 3
     elif what == "variant_unknown":
         o.grad_variant[pick % n.NR_NUM_BUCKETS] = 3 + pick % 4
+    elif what == "node_groups_one":
+        o.node_groups = 1
+    elif what == "node_groups_high":
+        o.node_groups = 18 + pick % 50
+    elif what == "node_groups_negative":
+        o.node_groups = -1 - pick % 5
     elif what == "store_too_deep":
         smax = L.nr_store_max_layers(b["prec"])
         deep = [k for k in range(n.NR_NUM_BUCKETS) if L.nr_bucket_lmax(k) > smax]

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     n, L = _lib()
     for name in n.EXPORTS:
         assert hasattr(L, name), name
-    assert L.nr_version() == 1
+    assert L.nr_version() == 2
 
 
 def test_status_strings():

@@ -57,9 +57,35 @@ def _check_against_oracle(nr, orc, batch, options):
     {"side_stream": 0, "split_tails": 0, "pack_tails": 0},
     {"split_tails": 3},   # no small-plan split
     {"split_tails": 4},   # the small-plan split only
+    {"node_groups": 2},   # (sample, Q) tilings: 32, 16, 8 and 3 points per wave
+    {"node_groups": 4},
+    {"node_groups": 8, "side_stream": 0},
+    {"node_groups": 17, "pack_tails": 0},
 ])
 def test_schedules_match_oracle(nr, orc, options):
     _check_against_oracle(nr, orc, _batch(501), options)
+
+
+@pytest.mark.parametrize("groups", [2, 4])
+def test_node_group_tilings_of_a_large_plan(nr, orc, groups):
+    """A plan large enough that the library's rules keep 64 points per wave
+    (4096 draws of 10 layers x 400 points), tiled with node groups instead:
+    sampled draws against the oracle."""
+    from paper_2509_06924_amd import inputs
+    batch = inputs.c2_batched()
+    prob = nr.Problem.from_batch(batch, options={"node_groups": groups})
+    Rhat = prob.reflectivity().cpu().numpy()
+    ll, g_rows, g_inst = (t.cpu().numpy() for t in prob.loglik_grad())
+    assert np.all(prob.item_status.cpu().numpy() == 0)
+    for b in (0, 2049, 4095):
+        rows = batch.rows_of(b)
+        Q, Robs, Rerr, dqq = batch.data_of(b)
+        Ro = orc.model_curve(rows, batch.scale[b], batch.bkg[b], Q, dqq)
+        check_R(Rhat[prob.out_off[b]:prob.out_off[b + 1]], Ro, what=f"R item {b}")
+        llo, go, gio = orc.loglik_grad_cs(rows, batch.scale[b], batch.bkg[b], Q, Robs, Rerr, dqq)
+        check_logL(ll[b], llo, logL_bound(Ro, Robs, Rerr), what=f"logL item {b}")
+        r0, r1 = batch.row_off[b], batch.row_off[b + 1]
+        check_grad(g_rows[r0:r1], g_inst[b], go, gio, what=f"grad item {b}, {groups} groups")
 
 
 def test_autotune_choice_and_cache(nr, orc, tmp_path):
@@ -67,7 +93,8 @@ def test_autotune_choice_and_cache(nr, orc, tmp_path):
     batch = inputs.c2_batched(n_items=512, L=6)
     cache = str(tmp_path / "tune.json")
     opts = autotune.tune(batch, cache=cache, reps=2)
-    assert set(opts) == {"grad_variant", "xcd_run", "pack_tails", "split_tails", "side_stream"}
+    assert set(opts) == {"grad_variant", "xcd_run", "pack_tails", "split_tails", "side_stream",
+                         "node_groups"}
     assert autotune.tune(batch, cache=cache) == opts  # served from the cache
     p_def = nr.Problem.from_batch(batch)
     p_tun = nr.Problem.from_batch(batch, options=opts)

@@ -130,11 +130,13 @@ def test_microsliced_layer_identities_on_device(nr, orc):
                          [(0, _sliced(1), 1.0, 1e-7), (0, _sliced(n), 1.0, 1e-7)], {})
     prob = nr.Problem.from_batch(batch)
     ll, g, _ = (t.cpu().numpy() for t in prob.loglik_grad())
-    assert abs(ll[1] - ll[0]) <= 1e-9 * abs(ll[0])
+    # measured on MI355X: 2e-15, 4e-13 and 2e-13 (1e-14, 1.2e-12 and 7e-13
+    # at 1000 slices)
+    assert abs(ll[1] - ll[0]) <= 1e-10 * abs(ll[0])
     g1 = g[0:3]
     gn = g[3:3 + n + 2]
-    assert np.allclose(gn[1:n + 1, 0], g1[1, 0], rtol=1e-7, atol=0)
-    assert abs(np.sum(gn[1:n + 1, 1]) - g1[1, 1]) <= 1e-7 * abs(g1[1, 1])
+    assert np.allclose(gn[1:n + 1, 0], g1[1, 0], rtol=1e-10, atol=0)
+    assert abs(np.sum(gn[1:n + 1, 1]) - g1[1, 1]) <= 1e-10 * abs(g1[1, 1])
 
 
 def _golden_deep():
