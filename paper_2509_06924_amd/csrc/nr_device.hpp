@@ -109,8 +109,15 @@ __device__ __forceinline__ int low_word(double t) {
 // to r^7 and cos r to r^6 (truncation below 1e-20 and 3.3e-18 on
 // |r| <= pi/128), then the angle-addition formulas with the tabulated sin and
 // cos of (k mod 128) pi/64.
-__device__ __forceinline__ void sincos_tab(const MathTables& T, double x, double* sn,
-                                           double* cs) {
+// The table-driven functions come in two halves so that a caller can issue
+// the LDS reads of one level well before it needs the values: *_issue forms
+// the reduced argument, its polynomial and the table reads, *_finish combines
+// them.  sincos_tab, exp_tab and cexp_tab are the two halves back to back.
+struct SinCosPart {
+  double sr, cr;  // sin r, cos r
+  double sa, ca;  // tabulated sin, cos of (k mod 128) pi/64
+};
+__device__ __forceinline__ SinCosPart sincos_issue(const MathTables& T, double x) {
   constexpr double k64OverPi = 20.371832715762604;
   constexpr double kP1 = 0.04908738521234052;
   constexpr double kP2 = 1.9135106236677394e-18;
@@ -120,25 +127,39 @@ __device__ __forceinline__ void sincos_tab(const MathTables& T, double x, double
   r = fma(-k, kP2, r);
   const int idx = low_word(t) & 127;
   const lds_double* row = (const lds_double*)(&T.sc[idx][0]);
-  const double sa = row[0], ca = row[1];
+  SinCosPart o;
+  o.sa = row[0];
+  o.ca = row[1];
   const double r2 = r * r;
   double ps = -0.0001984126984126984;          // -1/7!
   ps = fma(ps, r2, 0.008333333333333333);      //  1/5!
   ps = fma(ps, r2, -0.16666666666666666);      // -1/3!
-  const double sr = fma(r * r2, ps, r);
+  o.sr = fma(r * r2, ps, r);
   double pc = -0.001388888888888889;           // -1/6!
   pc = fma(pc, r2, 0.041666666666666664);      //  1/4!
   pc = fma(pc, r2, -0.5);                      // -1/2
-  const double cr = fma(r2, pc, 1.0);
-  *sn = fma(sa, cr, ca * sr);
-  *cs = fma(ca, cr, -(sa * sr));
+  o.cr = fma(r2, pc, 1.0);
+  return o;
+}
+__device__ __forceinline__ void sincos_finish(const SinCosPart& p, double* sn, double* cs) {
+  *sn = fma(p.sa, p.cr, p.ca * p.sr);
+  *cs = fma(p.ca, p.cr, -(p.sa * p.sr));
+}
+__device__ __forceinline__ void sincos_tab(const MathTables& T, double x, double* sn,
+                                           double* cs) {
+  sincos_finish(sincos_issue(T, x), sn, cs);
 }
 
 // e^x: x = (64 m + j) ln2/64 + r with ln2/64 split in two doubles,
 // |r| <= ln2/128, Taylor polynomial of e^r to r^5 (truncation below 3.5e-17
 // relative), times the tabulated 2^(j/64), scaled by 2^m.  The argument is
 // clamped to [-746, 710] first: +inf above ~709.8, 0 below ~-745.
-__device__ __forceinline__ double exp_tab(const MathTables& T, double x) {
+struct ExpPart {
+  double p;   // e^r
+  double tj;  // tabulated 2^(j/64)
+  int m;
+};
+__device__ __forceinline__ ExpPart exp_issue(const MathTables& T, double x) {
   constexpr double k64OverLn2 = 92.33248261689366;
   constexpr double kL1 = 0.010830424696249145;
   constexpr double kL2 = 3.623510646634843e-19;
@@ -149,22 +170,43 @@ __device__ __forceinline__ double exp_tab(const MathTables& T, double x) {
   r = fma(-n, kL2, r);
   const int ni = low_word(t);
   const int j = ni & 63;
-  const int m = ni >> 6;  // floor(n / 64)
+  ExpPart o;
+  o.m = ni >> 6;  // floor(n / 64)
+  o.tj = ((const lds_double*)(&T.e2[0]))[j];
   double p = 0.008333333333333333;   // 1/5!
   p = fma(p, r, 0.041666666666666664);
   p = fma(p, r, 0.16666666666666666);
   p = fma(p, r, 0.5);
   p = fma(p, r, 1.0);
-  p = fma(p, r, 1.0);
-  const double tj = ((const lds_double*)(&T.e2[0]))[j];
-  return ldexp(tj * p, m);
+  o.p = fma(p, r, 1.0);
+  return o;
+}
+__device__ __forceinline__ double exp_finish(const ExpPart& e) { return ldexp(e.tj * e.p, e.m); }
+__device__ __forceinline__ double exp_tab(const MathTables& T, double x) {
+  return exp_finish(exp_issue(T, x));
 }
 
-__device__ __forceinline__ cd cexp_tab(const MathTables& T, cd z) {
+template <class Re>
+struct CexpPart;
+template <>
+struct CexpPart<double> {
+  SinCosPart sc;
+  ExpPart ex;
+};
+__device__ __forceinline__ CexpPart<double> cexp_issue(const MathTables& T, cd z) {
+  CexpPart<double> o;
+  o.sc = sincos_issue(T, z.im);
+  o.ex = exp_issue(T, z.re);
+  return o;
+}
+__device__ __forceinline__ cd cexp_finish(const CexpPart<double>& p) {
   double s, c;
-  sincos_tab(T, z.im, &s, &c);
-  const double e = exp_tab(T, z.re);
+  sincos_finish(p.sc, &s, &c);
+  const double e = exp_finish(p.ex);
   return mk(e * c, e * s);
+}
+__device__ __forceinline__ cd cexp_tab(const MathTables& T, cd z) {
+  return cexp_finish(cexp_issue(T, z));
 }
 
 // Square of the fronting wavevector, kz0^2 = (Q/2)^2, formed as (0.25 q) q
@@ -230,13 +272,21 @@ __device__ __forceinline__ void sincos_f32(float x, float* sn, float* cs) {
   *cs = __builtin_amdgcn_cosf(u);
 }
 
-// Complex exponential in FP32 (the LDS tables are not used).
-__device__ __forceinline__ cf cexp_tab(const MathTables&, cf z) {
+// Complex exponential in FP32 (the LDS tables are not used; the issue half
+// only holds the argument).
+__device__ __forceinline__ cf cexp_f32(cf z) {
   float s, c;
   sincos_f32(z.im, &s, &c);
   const float e = exp_f32(z.re);
   return mk(e * c, e * s);
 }
+__device__ __forceinline__ cf cexp_tab(const MathTables&, cf z) { return cexp_f32(z); }
+template <>
+struct CexpPart<float> {
+  cf z;
+};
+__device__ __forceinline__ CexpPart<float> cexp_issue(const MathTables&, cf z) { return {z}; }
+__device__ __forceinline__ cf cexp_finish(const CexpPart<float>& p) { return cexp_f32(p.z); }
 
 // The FP32 root of w = x + i y, same branch and formulas as kz_root(double,
 // double); x is the FP64 difference kz0^2 - A rounded once to float, so the

@@ -69,6 +69,10 @@ struct F64 {
   static constexpr bool checkpoint(int lmax) { return lmax == 12 || lmax == 14 || lmax >= 28; }
   // the node's scheduling regions span several levels: at one wave per SIMD
   static constexpr bool grouped_regions(int lmax) { return min_waves(lmax, false) == 1; }
+  // one wave per SIMD leaves the latency of the table and record reads
+  // exposed: the recompute variant then issues each level's reads one level
+  // ahead of their use
+  static constexpr bool pipelined(int lmax) { return min_waves(lmax, false) == 1; }
 };
 struct F32 {
   using real = float;
@@ -94,6 +98,7 @@ struct F32 {
   // from 12 layers, at one or two waves per SIMD (12 layers 5 % faster, 14-28
   // equal or faster); not at 32-40 layers (3-5 % slower)
   static constexpr bool grouped_regions(int lmax) { return lmax >= 12 && lmax < 32; }
+  static constexpr bool pipelined(int) { return false; }
 };
 
 // ---------------------------------------------------------------------------
@@ -143,6 +148,21 @@ struct Layers {
       return at(m, fd);
     else
       return recf[med(m) * kRecF + ff];
+  }
+  // the whole record of medium m (loaded a level ahead by the pipelined sweeps)
+  struct Rec {
+    double A;
+    Re B, Nr, Ni, C, D;
+  };
+  __device__ __forceinline__ Rec rec_of(int m) const {
+    Rec r;
+    r.A = A(m);
+    r.B = B(m);
+    r.Nr = Nr(m);
+    r.Ni = Ni(m);
+    r.C = C(m);
+    r.D = D(m);
+    return r;
   }
   __device__ __forceinline__ double A(int m) const { return at(m, 0); }
   __device__ __forceinline__ Re B(int m) const { return get(m, 1, 0); }
@@ -732,32 +752,97 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
   // region and the adjoint is cut every kAdjGroup levels.  The kz, interface
   // and phase of one level do not depend on the state, so the scheduler
   // overlaps neighbouring levels' chains.
+  //
+  // Where the policy's pipelined says so (the one-wave FP64 kernels), both
+  // sweeps are software-pipelined instead: the region of one level also
+  // forms the next level's wavevector and interface and issues its LDS table
+  // (or cache) reads, and loads the layer record the region after it needs.
+  // Each read then has a whole level of work to arrive in; left to the
+  // compiler, a read was used about 10 instructions after its issue, and the
+  // one wave stalled on it.
   constexpr bool kGrouped = P::grouped_regions(LMAX);
   constexpr int kAdjGroup = kGrouped ? 8 : 1;
+  constexpr bool kPipe = P::pipelined(LMAX);
   Cx kzn = medium_root(L, kz0sq, LMAX + 1, edge).kz;
   Cx Pv = mk(Re(1), Re(0)), Qv = mk(Re(0), Re(0));
+  // Pipelined forward sweep: the region of level jj also forms level jj-1's
+  // wavevector and interface and issues its table reads, which level jj-1
+  // uses a region later; it loads the record of level jj-2.
+  struct FwdPre {
+    Cx kz;  // medium jj (jj = 0: the fronting medium)
+    Cx r;   // (w_jj - w_jj+1) s^2, r' without the Nevot-Croce factor
+    CexpPart<Re> f, e;
+  };
+  using Rec = typename Layers<P>::Rec;
+  auto fwd_pre = [&](int jj, Cx kzb, const Rec& rj) {
+    FwdPre o;
+    if (jj == 0) {
+      o.kz = kz0;
+    } else {
+      const double x = kz_real_part(kz0sq, rj.A);
+      edge |= (x == 0.0) & (rj.B == Re(0));
+      o.kz = kz_root(static_cast<Re>(x), -rj.B).kz;
+    }
+    const Cx s = crecip(o.kz + kzb);
+    o.r = mk(rj.Nr, rj.Ni) * (s * s);
+    o.f = cexp_issue(T, rj.C * (o.kz * kzb));
+    if (jj >= 1) o.e = cexp_issue(T, mk(rj.D * o.kz.im, -rj.D * o.kz.re));
+    return o;
+  };
+  if constexpr (kPipe) {
+    Rec R[LMAX + 1];
+    R[LMAX] = L.rec_of(LMAX);
+    if (LMAX >= 1) R[LMAX - 1] = L.rec_of(LMAX - 1);
+    FwdPre cur = fwd_pre(LMAX, kzn, R[LMAX]);
 #pragma unroll
-  for (int jj = LMAX; jj >= 0; --jj) {
-    const Cx kzc = (jj == 0) ? kz0 : medium_root(L, kz0sq, jj, edge).kz;
-    if (!CK || jj % 2 == 0) {
-      tapeP[CK ? jj / 2 : jj] = Pv;
-      tapeQ[CK ? jj / 2 : jj] = Qv;
+    for (int jj = LMAX; jj >= 0; --jj) {
+      if (jj >= 2) R[jj - 2] = L.rec_of(jj - 2);
+      FwdPre nxt;
+      if (jj >= 1) nxt = fwd_pre(jj - 1, cur.kz, R[jj - 1]);
+      if (!CK || jj % 2 == 0) {
+        tapeP[CK ? jj / 2 : jj] = Pv;
+        tapeQ[CK ? jj / 2 : jj] = Qv;
+      }
+      const Cx f = cexp_finish(cur.f);
+      const Cx rp = cur.r * f;
+      const Cx Pn = Pv + rp * Qv;
+      const Cx t = rp * Pv + Qv;
+      const Cx e = (jj >= 1) ? cexp_finish(cur.e) : mk(Re(1), Re(0));
+      if (jj < KS) {
+        ef.v[jj][0][lane] = e.re;
+        ef.v[jj][1][lane] = e.im;
+        ef.v[jj][2][lane] = f.re;
+        ef.v[jj][3][lane] = f.im;
+      }
+      Qv = (jj >= 1) ? e * t : t;
+      Pv = Pn;
+      if (jj >= 1) cur = nxt;
+      __builtin_amdgcn_sched_barrier(0);
     }
-    const Iface<Re> it = interface_coeffs(T, kzc, kzn, L.Nr(jj), L.Ni(jj), L.C(jj));
-    const Cx Pn = Pv + it.rp * Qv;
-    const Cx t = it.rp * Pv + Qv;
-    const Cx e = (jj >= 1) ? layer_phase(T, kzc, L.D(jj)) : mk(Re(1), Re(0));
-    if (jj < KS) {
-      ef.v[jj][0][lane] = e.re;
-      ef.v[jj][1][lane] = e.im;
-      ef.v[jj][2][lane] = it.f.re;
-      ef.v[jj][3][lane] = it.f.im;
+  } else {
+#pragma unroll
+    for (int jj = LMAX; jj >= 0; --jj) {
+      const Cx kzc = (jj == 0) ? kz0 : medium_root(L, kz0sq, jj, edge).kz;
+      if (!CK || jj % 2 == 0) {
+        tapeP[CK ? jj / 2 : jj] = Pv;
+        tapeQ[CK ? jj / 2 : jj] = Qv;
+      }
+      const Iface<Re> it = interface_coeffs(T, kzc, kzn, L.Nr(jj), L.Ni(jj), L.C(jj));
+      const Cx Pn = Pv + it.rp * Qv;
+      const Cx t = it.rp * Pv + Qv;
+      const Cx e = (jj >= 1) ? layer_phase(T, kzc, L.D(jj)) : mk(Re(1), Re(0));
+      if (jj < KS) {
+        ef.v[jj][0][lane] = e.re;
+        ef.v[jj][1][lane] = e.im;
+        ef.v[jj][2][lane] = it.f.re;
+        ef.v[jj][3][lane] = it.f.im;
+      }
+      Qv = (jj >= 1) ? e * t : t;
+      Pv = Pn;
+      kzn = kzc;
+      if (!kGrouped || jj == 0)
+        __builtin_amdgcn_sched_barrier(0x0100);  // only LDS reads may move across
     }
-    Qv = (jj >= 1) ? e * t : t;
-    Pv = Pn;
-    kzn = kzc;
-    if (!kGrouped || jj == 0)
-      __builtin_amdgcn_sched_barrier(0x0100);  // only LDS reads may move across
   }
   const Cx iP = crecip(Pv);
   const Cx r = Qv * iP;
@@ -815,7 +900,109 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
 
   Cx kzc = kz0;
   Re iac = Re(0);
-  if constexpr (!CK) {
+  // Pipelined adjoint: the region of level jj also forms level jj+1's
+  // wavevector and interface and issues its table (or cache) reads.
+  struct AdjPre {
+    RootT<Re> rn;  // medium jj + 1
+    Cx s2, kk, r;  // s^2, kz_jj kz_jj+1, (w_jj - w_jj+1) s^2
+    Cx fv, ev;     // f and e from the LDS cache (jj < KS)
+    CexpPart<Re> f, e;
+    Re C, D;
+  };
+  // (ri: the record of level jj, rn: that of medium jj + 1)
+  auto adj_pre = [&](int jj, Cx kzb, const Rec& ri, const Rec& rn) {
+    AdjPre o;
+    o.rn = kz_root(static_cast<Re>(kz_real_part(kz0sq, rn.A)), -rn.B);
+    o.C = ri.C;
+    const bool ph = jj >= 1;
+    o.D = ph ? ri.D : Re(0);
+    const Cx s = crecip(kzb + o.rn.kz);
+    o.s2 = s * s;
+    o.kk = kzb * o.rn.kz;
+    o.r = mk(ri.Nr, ri.Ni) * o.s2;
+    if (jj < KS) {
+      o.fv = mk(ef.v[jj][2][lane], ef.v[jj][3][lane]);
+      o.ev = ph ? mk(ef.v[jj][0][lane], ef.v[jj][1][lane]) : mk(Re(1), Re(0));
+    } else {
+      o.f = cexp_issue(T, o.C * o.kk);
+      if (ph) o.e = cexp_issue(T, mk(o.D * kzb.im, -o.D * kzb.re));
+    }
+    return o;
+  };
+  auto adj_level = [&](int jj, const AdjPre& p) {
+    Lev o;
+    o.rn = p.rn;
+    o.C = p.C;
+    o.D = p.D;
+    o.it.s2 = p.s2;
+    o.it.kk = p.kk;
+    o.it.f = (jj < KS) ? p.fv : cexp_finish(p.f);
+    o.it.rp = p.r * o.it.f;
+    o.e = (jj < 1) ? mk(Re(1), Re(0)) : (jj < KS) ? p.ev : cexp_finish(p.e);
+    return o;
+  };
+  // records of media 0 .. LMAX + 1, each loaded a region before its use
+  Rec RA[kPipe ? LMAX + 2 : 1];
+  auto load_rec = [&](int m) {
+    if (m <= LMAX + 1) RA[m] = L.rec_of(m);
+  };
+  if constexpr (kPipe && CK) {
+    // pairs of levels (jj, jj + 1), jj odd, after level 0: the region that
+    // finishes level jj issues level jj + 1's reads; the next one finishes
+    // level jj + 1, re-forms the state entering level jj, takes both adjoint
+    // steps and issues level jj + 2's reads
+    load_rec(0);
+    load_rec(1);
+    load_rec(2);
+    AdjPre cur = adj_pre(0, kzc, RA[0], RA[1]);
+    {
+      load_rec(3);
+      const AdjPre nxt = adj_pre(1, cur.rn.kz, RA[1], RA[2]);
+      const Lev l0 = adj_level(0, cur);
+      step(0, l0, tapeP[0], tapeQ[0], kzc, iac);
+      kzc = l0.rn.kz;
+      iac = l0.rn.inv_abs2;
+      cur = nxt;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int jj = 1; jj <= LMAX; jj += 2) {
+      load_rec(jj + 3);
+      const AdjPre pb = adj_pre(jj + 1, cur.rn.kz, RA[jj + 1], RA[jj + 2]);
+      const Lev la = adj_level(jj, cur);
+      __builtin_amdgcn_sched_barrier(0);
+      load_rec(jj + 4);
+      AdjPre nxt;
+      if (jj + 1 < LMAX) nxt = adj_pre(jj + 2, pb.rn.kz, RA[jj + 2], RA[jj + 3]);
+      const Lev lb = adj_level(jj + 1, pb);
+      const Cx P1 = tapeP[(jj + 1) / 2], Q1 = tapeQ[(jj + 1) / 2];
+      const Cx P0 = P1 + lb.it.rp * Q1;
+      const Cx Q0 = lb.e * (lb.it.rp * P1 + Q1);
+      step(jj, la, P0, Q0, kzc, iac);
+      step(jj + 1, lb, P1, Q1, la.rn.kz, la.rn.inv_abs2);
+      kzc = lb.rn.kz;
+      iac = lb.rn.inv_abs2;
+      if (jj + 1 < LMAX) cur = nxt;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  } else if constexpr (kPipe) {
+    load_rec(0);
+    load_rec(1);
+    load_rec(2);
+    AdjPre cur = adj_pre(0, kzc, RA[0], RA[1]);
+#pragma unroll
+    for (int jj = 0; jj <= LMAX; ++jj) {
+      load_rec(jj + 3);
+      AdjPre nxt;
+      if (jj < LMAX) nxt = adj_pre(jj + 1, cur.rn.kz, RA[jj + 1], RA[jj + 2]);
+      const Lev lv = adj_level(jj, cur);
+      step(jj, lv, tapeP[jj], tapeQ[jj], kzc, iac);
+      kzc = lv.rn.kz;
+      iac = lv.rn.inv_abs2;
+      if (jj < LMAX) cur = nxt;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  } else if constexpr (!CK) {
 #pragma unroll
     for (int jj = 0; jj <= LMAX; ++jj) {
       const Lev lv = level(jj, kzc);

@@ -32,10 +32,10 @@ BUDGET = {
         ("F64", 14, 0, 0, 0, 0): (255, 0, 100, 2, 19760),
     },
     ("nr_kernels_bucket.hip", ("F64", 24)): {
-        ("F64", 24, 0, 0, 0, 0): (256, 212, 0, 1, 38512),
+        ("F64", 24, 0, 0, 0, 0): (256, 238, 0, 1, 38512),
     },
     ("nr_kernels_bucket.hip", ("F64", 40)): {
-        ("F64", 40, 0, 0, 0, 0): (256, 256, 344, 1, 39024),
+        ("F64", 40, 0, 0, 0, 0): (256, 256, 448, 1, 39024),
     },
     ("nr_kernels_f32.hip", ()): {
         ("F32", 8, 1, 0, 0, 0): (241, 0, 0, 2, 17008),
