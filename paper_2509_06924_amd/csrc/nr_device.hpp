@@ -53,6 +53,15 @@ template <class T>
 __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
   return mk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
 }
+// conj(a) b + c and a b + c as four FMAs each.
+template <class T>
+__device__ __forceinline__ cx<T> cmulc_add(cx<T> a, cx<T> b, cx<T> c) {
+  return mk(fma(a.re, b.re, fma(a.im, b.im, c.re)), fma(a.re, b.im, fma(-a.im, b.re, c.im)));
+}
+template <class T>
+__device__ __forceinline__ cx<T> cmul_add(cx<T> a, cx<T> b, cx<T> c) {
+  return mk(fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im)));
+}
 template <class T>
 __device__ __forceinline__ T cabs2(cx<T> a) { return a.re * a.re + a.im * a.im; }
 __device__ __forceinline__ cd widen(cd a) { return a; }

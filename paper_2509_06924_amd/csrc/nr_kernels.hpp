@@ -55,7 +55,11 @@ struct F64 {
   using real = double;
   static constexpr int kStoreMax = kStoreMaxLayers;
   static constexpr int kSlimMax = 6;
-  static constexpr int min_waves(int lmax, bool store) { return (!store && lmax <= 14) ? 2 : 1; }
+  // (packed = a tail or split unit, whose extra bookkeeping the 4-layer store
+  // kernel does not fit into two waves' registers)
+  static constexpr int min_waves(int lmax, bool store, bool packed = false) {
+    return ((!store && lmax <= 14) || (store && lmax <= 4 && !packed)) ? 2 : 1;
+  }
   // recompute variant: levels whose phase and Nevot-Croce factor are kept in
   // LDS (2 KB per level per wave; ~36 KB of the 40 KB a wave may use at one
   // wave per SIMD)
@@ -84,7 +88,9 @@ struct F32 {
   // tape keeps the spill small (none at 18, 204 B per lane at 24, 364 B at
   // 28), and two waves ran 23, 22 and 4 % faster than one at 20, 24 and 28
   // layers; at 32-40 layers (516-836 B) they lost 6-27 %.
-  static constexpr int min_waves(int lmax, bool) { return (lmax <= 28 && lmax != 16) ? 2 : 1; }
+  static constexpr int min_waves(int lmax, bool, bool = false) {
+    return (lmax <= 28 && lmax != 16) ? 2 : 1;
+  }
   // 1 KB per level; up to 28 layers the LDS of a kernel that may share the
   // SIMD with a second wave stays within 20 KB; up to 10 layers the kernel
   // fits three waves per SIMD in registers, and 9 levels keep its LDS within
@@ -274,16 +280,16 @@ __device__ __forceinline__ double node_reflectivity(const MathTables& T, const L
   for (int jj = N; jj >= 1; --jj) {
     const Cx kzc = medium_root(L, kz0sq, jj).kz;
     const Iface<Re> it = interface_coeffs(T, kzc, kzn, L.Nr(jj), L.Ni(jj), L.C(jj));
-    const Cx Pn = Pv + it.rp * Qv;
-    const Cx t = it.rp * Pv + Qv;
+    const Cx Pn = cmul_add(it.rp, Qv, Pv);
+    const Cx t = cmul_add(it.rp, Pv, Qv);
     Qv = layer_phase(T, kzc, L.D(jj)) * t;
     Pv = Pn;
     kzn = kzc;
   }
   {
     const Iface<Re> it = interface_coeffs(T, fronting_kz<P>(q), kzn, L.Nr(0), L.Ni(0), L.C(0));
-    const Cx Pn = Pv + it.rp * Qv;
-    Qv = it.rp * Pv + Qv;
+    const Cx Pn = cmul_add(it.rp, Qv, Pv);
+    Qv = cmul_add(it.rp, Pv, Qv);
     Pv = Pn;
   }
   return (double)cabs2(Qv * crecip(Pv));
@@ -491,27 +497,20 @@ __global__ __launch_bounds__(64) void k_loglik(KernelArgs a) {
 // Adjoint of one interface/layer step (shared by both gradient variants).
 // In: state (Ps, Qs) entering level j (= state of level j+1), cotangents
 // (Pb, Qb) of the state leaving level j, kz_j, kz_{j+1}, the interface
-// coefficients, the phase e_j (j >= 1).  Out: cotangents of the state entering
-// the level, kzbar contributions, and the d / sigma accumulators.
+// coefficients, the phase e_j (j >= 1) and the running kzbar_j (the
+// contribution of level j - 1).  Out: cotangents of the state entering the
+// level, kzbar_j complete and kzbar_{j+1}'s first part, and the terms of the
+// d and sigma accumulators.
 // ---------------------------------------------------------------------------
 template <class Re>
 struct AdjStep {
   cx<Re> Pb, Qb;   // cotangents of the state entering level j
-  cx<Re> kzb_c;    // contribution to kzbar_j
+  cx<Re> kzb_c;    // kzbar_j: the running sum passed in plus this level's part
   cx<Re> kzb_n;    // contribution to kzbar_{j+1}
   cx<Re> ub;       // cotangent of the Nevot-Croce exponent
   cx<Re> w;        // conj(e) ebar (phase levels)
 };
 
-// conj(a) b + c and a b + c as four FMAs each.
-template <class Re>
-__device__ __forceinline__ cx<Re> cmulc_add(cx<Re> a, cx<Re> b, cx<Re> c) {
-  return mk(fma(a.re, b.re, fma(a.im, b.im, c.re)), fma(a.re, b.im, fma(-a.im, b.re, c.im)));
-}
-template <class Re>
-__device__ __forceinline__ cx<Re> cmul_add(cx<Re> a, cx<Re> b, cx<Re> c) {
-  return mk(fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im)));
-}
 
 // Per level (cotangent convention zbar = dl/dRe z + i dl/dIm z):
 //   t = r' P + Qv;  ebar = conj(t) Qbar;  tbar = conj(e) Qbar
@@ -526,7 +525,8 @@ __device__ __forceinline__ cx<Re> cmul_add(cx<Re> a, cx<Re> b, cx<Re> c) {
 template <class Re>
 __device__ __forceinline__ AdjStep<Re> adjoint_step(cx<Re> Ps, cx<Re> Qs, cx<Re> Pb, cx<Re> Qb,
                                                     cx<Re> kzc, cx<Re> kzn, const Iface<Re>& it,
-                                                    Re C, bool has_phase, cx<Re> e, Re D) {
+                                                    Re C, bool has_phase, cx<Re> e, Re D,
+                                                    cx<Re> kzbc) {
   using Cx = cx<Re>;
   AdjStep<Re> o;
   Cx tb;
@@ -548,7 +548,7 @@ __device__ __forceinline__ AdjStep<Re> adjoint_step(cx<Re> Ps, cx<Re> Qs, cx<Re>
   const Cx Y = cmulc(it.s2, rb);
   const Cx Zc = mk(fma(Re(2), Y.re, X.re), fma(Re(2), Y.im, X.im));
   const Cx Zn = mk(fma(Re(-2), Y.re, X.re), fma(Re(-2), Y.im, X.im));
-  o.kzb_c = cmulc(kzn, Zc);
+  o.kzb_c = cmulc_add(kzn, Zc, kzbc);
   o.kzb_n = cmulc(kzc, Zn);
   if (has_phase) {
     o.kzb_c.re = fma(-D, o.w.im, o.kzb_c.re);
@@ -565,27 +565,32 @@ __device__ __forceinline__ void acc_re_dot(double& acc, cd a, cd b) {
 __device__ __forceinline__ void acc_re_dot(double& acc, cf a, cf b) {
   acc += (double)(a.re * b.re + a.im * b.im);
 }
-// acc += 2 Im(kz conj(w)) (the thickness derivative), in FP64.
+// The accumulators hold fixed multiples of the sums they stand for; the
+// factors are applied once, when the record is written (kHdScale, kHwScale).
+//
+// acc += Im(kz conj(w)): half the thickness derivative 2 Im(kz conj(w)), in FP64.
+constexpr double kHdScale = 2.0;
 __device__ __forceinline__ void acc_dd(double& acc, cd kz, cd w) {
-  acc = fma(2.0, fma(kz.im, w.re, -(kz.re * w.im)), acc);
+  acc = fma(kz.im, w.re, fma(-kz.re, w.im, acc));
 }
 __device__ __forceinline__ void acc_dd(double& acc, cf kz, cf w) {
-  acc += 2.0 * (double)(kz.im * w.re - kz.re * w.im);
+  acc += (double)(kz.im * w.re - kz.re * w.im);
 }
-// acc += wbar = conj(dkz/dw) kzbar = conj(1/(2 kz)) kzbar = kz kzbar / (2 |kz|^2),
-// and with RES also sw += Re(wbar) (the node's sum over media, for dR/dq:
-// every w_j moves with kz0^2, dw_j/dq = kz0).
+// acc += 2 wbar, wbar = conj(dkz/dw) kzbar = conj(1/(2 kz)) kzbar = kz kzbar / (2 |kz|^2),
+// and with RES also sw += 2 Re(wbar) (the node's sum over media, for dR/dq:
+// every w_j moves with kz0^2, dw_j/dq = kz0).  Doubling is exact, so the
+// halved record equals the sum of the wbar terms bit for bit.
+constexpr double kHwScale = 0.5;
 template <bool RES>
 __device__ __forceinline__ void acc_wbar(cd& acc, double& sw, cd kz, double inv_abs2, cd kzb) {
   const cd p = kz * kzb;
-  const double h = 0.5 * inv_abs2;
-  acc.re = fma(h, p.re, acc.re);
-  acc.im = fma(h, p.im, acc.im);
-  if constexpr (RES) sw = fma(h, p.re, sw);
+  acc.re = fma(inv_abs2, p.re, acc.re);
+  acc.im = fma(inv_abs2, p.im, acc.im);
+  if constexpr (RES) sw = fma(inv_abs2, p.re, sw);
 }
 template <bool RES>
 __device__ __forceinline__ void acc_wbar(cd& acc, double& sw, cf kz, float inv_abs2, cf kzb) {
-  const cd v = widen((0.5f * inv_abs2) * (kz * kzb));
+  const cd v = widen(inv_abs2 * (kz * kzb));
   acc += v;
   if constexpr (RES) sw += v.re;
 }
@@ -667,8 +672,8 @@ __device__ __forceinline__ double node_grad_store(const MathTables& T, const Lay
     }
     tape_put(tp.P[jj], lane, Pv);
     tape_put(tp.Qv[jj], lane, Qv);
-    const Cx Pn = Pv + it.rp * Qv;
-    const Cx t = it.rp * Pv + Qv;
+    const Cx Pn = cmul_add(it.rp, Qv, Pv);
+    const Cx t = cmul_add(it.rp, Pv, Qv);
     if (jj >= 1) {
       const Cx e = layer_phase(T, kz[jj], L.D(jj));
       tape_put(tp.E[jj], lane, e);
@@ -701,9 +706,9 @@ __device__ __forceinline__ double node_grad_store(const MathTables& T, const Lay
     const Cx Qs = tape_get(tp.Qv[jj], lane);
     const bool ph = jj >= 1;
     const Cx e = ph ? tape_get(tp.E[jj], lane) : mk(Re(1), Re(0));
-    const AdjStep<Re> st =
-        adjoint_step(Ps, Qs, Pb, Qb, kz[jj], kz[jj + 1], it, C, ph, e, ph ? L.D(jj) : Re(0));
-    kzbc += st.kzb_c;
+    const AdjStep<Re> st = adjoint_step(Ps, Qs, Pb, Qb, kz[jj], kz[jj + 1], it, C, ph, e,
+                                        ph ? L.D(jj) : Re(0), kzbc);
+    kzbc = st.kzb_c;
     acc_re_dot(acc.Hs[jj + 1], st.ub, it.kk);
     if (ph) {
       acc_dd(acc.Hd[jj], kz[jj], st.w);
@@ -805,8 +810,8 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
       }
       const Cx f = cexp_finish(cur.f);
       const Cx rp = cur.r * f;
-      const Cx Pn = Pv + rp * Qv;
-      const Cx t = rp * Pv + Qv;
+      const Cx Pn = cmul_add(rp, Qv, Pv);
+      const Cx t = cmul_add(rp, Pv, Qv);
       const Cx e = (jj >= 1) ? cexp_finish(cur.e) : mk(Re(1), Re(0));
       if (jj < KS) {
         ef.v[jj][0][lane] = e.re;
@@ -828,8 +833,8 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
         tapeQ[CK ? jj / 2 : jj] = Qv;
       }
       const Iface<Re> it = interface_coeffs(T, kzc, kzn, L.Nr(jj), L.Ni(jj), L.C(jj));
-      const Cx Pn = Pv + it.rp * Qv;
-      const Cx t = it.rp * Pv + Qv;
+      const Cx Pn = cmul_add(it.rp, Qv, Pv);
+      const Cx t = cmul_add(it.rp, Pv, Qv);
       const Cx e = (jj >= 1) ? layer_phase(T, kzc, L.D(jj)) : mk(Re(1), Re(0));
       if (jj < KS) {
         ef.v[jj][0][lane] = e.re;
@@ -883,8 +888,8 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
   auto step = [&](int jj, const Lev& lv, Cx Ps, Cx Qs, Cx kzc, Re iac) {
     const bool ph = jj >= 1;
     const AdjStep<Re> st =
-        adjoint_step(Ps, Qs, Pb, Qb, kzc, lv.rn.kz, lv.it, lv.C, ph, lv.e, lv.D);
-    kzbc += st.kzb_c;
+        adjoint_step(Ps, Qs, Pb, Qb, kzc, lv.rn.kz, lv.it, lv.C, ph, lv.e, lv.D, kzbc);
+    kzbc = st.kzb_c;
     if constexpr (RES)
       if (jj == 0) Hq = fma(0.5 * c, (double)kzbc.re, Hq);
     acc_re_dot(acc.Hs[jj + 1], st.ub, lv.it.kk);
@@ -976,8 +981,8 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
       if (jj + 1 < LMAX) nxt = adj_pre(jj + 2, pb.rn.kz, RA[jj + 2], RA[jj + 3]);
       const Lev lb = adj_level(jj + 1, pb);
       const Cx P1 = tapeP[(jj + 1) / 2], Q1 = tapeQ[(jj + 1) / 2];
-      const Cx P0 = P1 + lb.it.rp * Q1;
-      const Cx Q0 = lb.e * (lb.it.rp * P1 + Q1);
+      const Cx P0 = cmul_add(lb.it.rp, Q1, P1);
+      const Cx Q0 = lb.e * cmul_add(lb.it.rp, P1, Q1);
       step(jj, la, P0, Q0, kzc, iac);
       step(jj + 1, lb, P1, Q1, la.rn.kz, la.rn.inv_abs2);
       kzc = lb.rn.kz;
@@ -1025,8 +1030,8 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
       const Lev la = level(jj, kzc);
       const Lev lb = level(jj + 1, la.rn.kz);
       const Cx P1 = tapeP[(jj + 1) / 2], Q1 = tapeQ[(jj + 1) / 2];
-      const Cx P0 = P1 + lb.it.rp * Q1;
-      const Cx Q0 = lb.e * (lb.it.rp * P1 + Q1);
+      const Cx P0 = cmul_add(lb.it.rp, Q1, P1);
+      const Cx Q0 = lb.e * cmul_add(lb.it.rp, P1, Q1);
       step(jj, la, P0, Q0, kzc, iac);
       step(jj + 1, lb, P1, Q1, la.rn.kz, la.rn.inv_abs2);
       kzc = lb.rn.kz;
@@ -1036,7 +1041,7 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
     }
   }
   // Hq += c dR/dq (seeded): dkz0/dq = 1/2 (added at level 0), dw_j/dq = kz0
-  if constexpr (RES) Hq = fma(0.5 * q * c, sw, Hq);
+  if constexpr (RES) Hq = fma(0.25 * q * c, sw, Hq);  // sw holds 2 sum Re(wbar)
   return (double)cabs2(r);
 }
 
@@ -1051,7 +1056,8 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
 //   [3 + 4NR]      d/d(dQ/Q) (relative resolution)
 // ---------------------------------------------------------------------------
 template <class P, int LMAX, bool STORE, bool TAIL, bool RES, bool SPLIT = false>
-__global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(KernelArgs a) {
+__global__ __launch_bounds__(64, P::min_waves(LMAX, STORE, TAIL || SPLIT)) void k_loglik_grad(
+    KernelArgs a) {
   static_assert(!(STORE && RES), "the resolution derivative has the recompute form only");
   static_assert(!(TAIL && SPLIT), "a unit is packed or split, not both");
   using Re = typename P::real;
@@ -1158,6 +1164,7 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(K
   flag(a.item_status, u.item, bits);
 
   const int NR = N + 2;
+  const double fw = kHwScale * fac, fd = kHdScale * fac;
   // record of 4 + 4 NR doubles; the last field is the resolution sum (0
   // outside the RES form, written all the same so that the records of
   // consecutive units form one contiguous store)
@@ -1193,9 +1200,9 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(K
 #pragma unroll
     for (int m = 0; m < LMAX + 2; ++m) {
       if (m < NR) {
-        seg_put(3 + m, fac * acc.Hw[m].re);
-        seg_put(3 + NR + m, fac * acc.Hw[m].im);
-        seg_put(3 + 2 * NR + m, fac * acc.Hd[m]);
+        seg_put(3 + m, fw * acc.Hw[m].re);
+        seg_put(3 + NR + m, fw * acc.Hw[m].im);
+        seg_put(3 + 2 * NR + m, fd * acc.Hd[m]);
         seg_put(3 + 3 * NR + m, fac * acc.Hs[m]);
       }
     }
@@ -1218,9 +1225,9 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE)) void k_loglik_grad(K
 #pragma unroll
   for (int m = 0; m < LMAX + 2; ++m) {
     if (m < NR) {
-      const double wr = wave_sum(fac * acc.Hw[m].re);
-      const double wi = wave_sum(fac * acc.Hw[m].im);
-      const double dd = wave_sum(fac * acc.Hd[m]);
+      const double wr = wave_sum(fw * acc.Hw[m].re);
+      const double wi = wave_sum(fw * acc.Hw[m].im);
+      const double dd = wave_sum(fd * acc.Hd[m]);
       const double ss = wave_sum(fac * acc.Hs[m]);
       if (lane == 0) {
         stage[3 + m] = wr;

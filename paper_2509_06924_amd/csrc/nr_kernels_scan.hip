@@ -295,8 +295,8 @@ __global__ __launch_bounds__(64 * NW, 2) void k_loglik_grad_scan(KernelArgs a) {
         const cd Qt = mk(TP(t, 2), TP(t, 3));
         const bool ph = jj >= 1;
         const AdjStep<double> st =
-            adjoint_step(Pt, Qt, Pb, Qb, rc.kz, rn.kz, lv.it, lv.C, ph, lv.e, lv.D);
-        kzbc += st.kzb_c;
+            adjoint_step(Pt, Qt, Pb, Qb, rc.kz, rn.kz, lv.it, lv.C, ph, lv.e, lv.D, kzbc);
+        kzbc = st.kzb_c;
         if constexpr (RES)
           if (jj == 0) Hq = fma(0.5 * dq_dres * tk, kzbc.re, Hq);
         {
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_loglik_grad_scan(KernelArgs a) {
         }
       }
     }
-    if constexpr (RES) Hq = fma(0.5 * q * dq_dres * tk, sw, Hq);
+    if constexpr (RES) Hq = fma(0.25 * q * dq_dres * tk, sw, Hq);  // sw: 2 sum Re(wbar)
   }
 
   // ---- the point's likelihood and seed (uniform over the lanes) ----
@@ -346,6 +346,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_loglik_grad_scan(KernelArgs a) {
     ghat = -(Rhat - a.r_obs[qoff + i]) / (e * e);
   }
   const double fac = ghat * sc;
+  const double fw = kHwScale * fac, fd = kHdScale * fac;
   if (__ballot(edge) != 0) bits |= kItemEdgeSingular;
   if (lane == 0) flag(a.item_status, item, bits);
 
@@ -384,16 +385,16 @@ __global__ __launch_bounds__(64 * NW, 2) void k_loglik_grad_scan(KernelArgs a) {
     for (int t = 0; t < CHT; ++t) {
       if (t < n) {
         const int m = lo + t;
-        rec[3 + m] = fac * AC(t, 0);
-        rec[3 + NR + m] = fac * AC(t, 1);
-        rec[3 + 2 * NR + m] = fac * AC(t, 2);
+        rec[3 + m] = fw * AC(t, 0);
+        rec[3 + NR + m] = fw * AC(t, 1);
+        rec[3 + 2 * NR + m] = fd * AC(t, 2);
         rec[3 + 3 * NR + m] = fac * AC(t, 3);
       }
     }
     if (hi == NL) {  // the backing medium N + 1
-      rec[3 + NL] = fac * bnd[0];
-      rec[3 + NR + NL] = fac * bnd[1];
-      rec[3 + 2 * NR + NL] = fac * bnd[2];
+      rec[3 + NL] = fw * bnd[0];
+      rec[3 + NR + NL] = fw * bnd[1];
+      rec[3 + 2 * NR + NL] = fd * bnd[2];
       rec[3 + 3 * NR + NL] = fac * bnd[3];
     }
   }
