@@ -41,6 +41,9 @@ BUDGET = {
         ("F32", 8, 1, 0, 0, 0): (256, 0, 0, 2, 17008),
         ("F32", 10, 0, 0, 0, 0): (168, 0, 0, 3, 12464),
     },
+    ("nr_kernels_bucket.hip", ("F32", 20)): {
+        ("F32", 20, 0, 0, 0, 0): (256, 0, 52, 2, 19952),
+    },
     ("nr_kernels_bucket.hip", ("F32", 24)): {
         ("F32", 24, 0, 0, 0, 0): (256, 0, 212, 2, 20080),
     },
