@@ -74,14 +74,26 @@ struct Lvl {
   double C, D;
 };
 
-__device__ __forceinline__ Lvl level_coeffs(const MathTables& T, const Layers<F64>& L, int jj,
+// (r: the record of level jj, loaded ahead by the caller)
+__device__ __forceinline__ Lvl level_coeffs(const MathTables& T, const Layers<F64>::Rec& r, int jj,
                                             cd kzc, cd kzn) {
   Lvl o;
-  o.C = L.C(jj);
-  o.D = (jj >= 1) ? L.D(jj) : 0.0;
-  o.it = interface_coeffs(T, kzc, kzn, L.Nr(jj), L.Ni(jj), o.C);
+  o.C = r.C;
+  o.D = (jj >= 1) ? r.D : 0.0;
+  o.it = interface_coeffs(T, kzc, kzn, r.Nr, r.Ni, o.C);
   o.e = (jj >= 1) ? layer_phase(T, kzc, o.D) : mk(1.0, 0.0);
   return o;
+}
+
+// kz of a medium from its record, recording an exact zero of w (the edge).
+__device__ __forceinline__ RootT<double> rec_root(const Layers<F64>::Rec& r, double kz0sq,
+                                                  bool& edge) {
+  const double x = kz_real_part(kz0sq, r.A);
+  edge |= (x == 0.0) & (r.B == 0.0);
+  return kz_root(x, -r.B);
+}
+__device__ __forceinline__ RootT<double> rec_root(const Layers<F64>::Rec& r, double kz0sq) {
+  return kz_root(kz_real_part(kz0sq, r.A), -r.B);
 }
 
 }  // namespace
@@ -173,13 +185,17 @@ __global__ __launch_bounds__(64 * NW, 2) void k_loglik_grad_scan(KernelArgs a) {
     //    r' and e are kept in its tape slot for the re-run in step 3
     M2 X = m2_identity();
     if (own) {
-      cd kzn = medium_root(L, kz0sq, hi, edge).kz;
+      // each level's record (per-lane vector loads) is loaded a level ahead
+      cd kzn = rec_root(L.rec_of(hi), kz0sq, edge).kz;
+      Layers<F64>::Rec rnx = L.rec_of(hi - 1);
 #pragma unroll
       for (int t = CHT - 1; t >= 0; --t) {
         if (t < n) {
           const int jj = lo + t;
-          const cd kzc = (jj == 0) ? kz0 : medium_root(L, kz0sq, jj, edge).kz;
-          const Lvl lv = level_coeffs(s.tab, L, jj, kzc, kzn);
+          const Layers<F64>::Rec rc = rnx;
+          if (t >= 1) rnx = L.rec_of(jj - 1);
+          const cd kzc = (jj == 0) ? kz0 : rec_root(rc, kz0sq, edge).kz;
+          const Lvl lv = level_coeffs(s.tab, rc, jj, kzc, kzn);
           TP(t, 0) = lv.it.rp.re;
           TP(t, 1) = lv.it.rp.im;
           TP(t, 2) = lv.e.re;
@@ -277,20 +293,25 @@ __global__ __launch_bounds__(64 * NW, 2) void k_loglik_grad_scan(KernelArgs a) {
       }
     }
     double sw = 0.0;
+    // records a level ahead: ri of level jj, rm of medium jj + 1
+    Layers<F64>::Rec ri = L.rec_of(lo), rm = L.rec_of(lo + 1);
     RootT<double> rc;
     if (lo == 0) {
       rc.kz = kz0;
       rc.inv_abs2 = 0.0;
     } else {
-      rc = medium_root(L, kz0sq, lo);
+      rc = rec_root(ri, kz0sq);
     }
     cd kzbc = mk(0.0, 0.0);
 #pragma unroll
     for (int t = 0; t < CHT; ++t) {
       if (t < n) {
         const int jj = lo + t;
-        const RootT<double> rn = medium_root(L, kz0sq, jj + 1);
-        const Lvl lv = level_coeffs(s.tab, L, jj, rc.kz, rn.kz);
+        const Layers<F64>::Rec rnext = L.rec_of(jj + 2);
+        const RootT<double> rn = rec_root(rm, kz0sq);
+        const Lvl lv = level_coeffs(s.tab, ri, jj, rc.kz, rn.kz);
+        ri = rm;
+        rm = rnext;
         const cd Pt = mk(TP(t, 0), TP(t, 1));
         const cd Qt = mk(TP(t, 2), TP(t, 3));
         const bool ph = jj >= 1;
