@@ -200,9 +200,9 @@ __global__ __launch_bounds__(64 * NW, 2) void k_loglik_grad_scan(KernelArgs a) {
           TP(t, 1) = lv.it.rp.im;
           TP(t, 2) = lv.e.re;
           TP(t, 3) = lv.e.im;
-          const cd a0 = X.a + lv.it.rp * X.c, b0 = X.b + lv.it.rp * X.d;
-          X.c = lv.e * (lv.it.rp * X.a + X.c);
-          X.d = lv.e * (lv.it.rp * X.b + X.d);
+          const cd a0 = cmul_add(lv.it.rp, X.c, X.a), b0 = cmul_add(lv.it.rp, X.d, X.b);
+          X.c = lv.e * cmul_add(lv.it.rp, X.a, X.c);
+          X.d = lv.e * cmul_add(lv.it.rp, X.b, X.d);
           X.a = a0;
           X.b = b0;
           kzn = kzc;
@@ -277,17 +277,32 @@ __global__ __launch_bounds__(64 * NW, 2) void k_loglik_grad_scan(KernelArgs a) {
     //    of step 1; each slot then holds the state entering its level
     {
       cd Pv = Ps, Qv = Qs;
+      // (each slot's r' and e are read a level ahead of their use)
+      // (slot n - 1 found by a compile-time loop: the register tape takes
+      // no runtime index)
+      cd rpn = mk(0.0, 0.0), en = mk(0.0, 0.0);
+#pragma unroll
+      for (int t = 0; t < CHT; ++t) {
+        if (t == n - 1) {
+          rpn = mk(TP(t, 0), TP(t, 1));
+          en = mk(TP(t, 2), TP(t, 3));
+        }
+      }
 #pragma unroll
       for (int t = CHT - 1; t >= 0; --t) {
         if (t < n) {
-          const cd rp = mk(TP(t, 0), TP(t, 1));
-          const cd e = mk(TP(t, 2), TP(t, 3));
+          const cd rp = rpn;
+          const cd e = en;
+          if (t >= 1) {
+            rpn = mk(TP(t - 1, 0), TP(t - 1, 1));
+            en = mk(TP(t - 1, 2), TP(t - 1, 3));
+          }
           TP(t, 0) = Pv.re;
           TP(t, 1) = Pv.im;
           TP(t, 2) = Qv.re;
           TP(t, 3) = Qv.im;
-          const cd Pn = Pv + rp * Qv;
-          Qv = e * (rp * Pv + Qv);  // e = 1 at level 0
+          const cd Pn = cmul_add(rp, Qv, Pv);
+          Qv = e * cmul_add(rp, Pv, Qv);  // e = 1 at level 0
           Pv = Pn;
         }
       }

@@ -53,7 +53,7 @@ BUDGET = {
     ("nr_kernels_scan.hip", ()): {
         ("scan", 8, 1, 0): (253, 0, 0, 2, 19216),
         ("scan", 8, 2, 0): (254, 0, 0, 2, 35808),
-        ("scan", 8, 4, 0): (256, 0, 140, 2, 68784),
+        ("scan", 8, 4, 0): (256, 0, 132, 2, 68784),
     },
 }
 
