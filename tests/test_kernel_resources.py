@@ -48,7 +48,7 @@ BUDGET = {
         ("F32", 24, 0, 0, 0, 0): (256, 0, 204, 2, 20080),
     },
     ("nr_kernels_bucket.hip", ("F32", 40)): {
-        ("F32", 40, 0, 0, 0, 0): (256, 210, 0, 1, 40048),
+        ("F32", 40, 0, 0, 0, 0): (256, 228, 0, 1, 40048),
     },
     ("nr_kernels_scan.hip", ()): {
         ("scan", 8, 1, 0): (253, 0, 0, 2, 19216),
