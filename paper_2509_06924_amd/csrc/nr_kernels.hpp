@@ -104,10 +104,13 @@ struct F32 {
   // from 12 layers, at one or two waves per SIMD (12 layers 5 % faster, 14-28
   // equal or faster); not at 32-40 layers (3-5 % slower)
   static constexpr bool grouped_regions(int lmax) { return lmax >= 12 && lmax < 32; }
-  // the one-wave kernels read their records and LDS cache a level ahead, as
-  // in FP64 (ragged FP32 batch 29.6 -> 25.9 ms; the exponentials are the
-  // hardware functions, so there are no table reads to issue early)
-  static constexpr bool pipelined(int lmax) { return min_waves(lmax, false) == 1; }
+  // from 12 layers the kernels read their records and LDS cache a level
+  // ahead, as the one-wave FP64 kernels do (the exponentials are the
+  // hardware functions, so there are no table reads to issue early): the
+  // one-wave kernels (16, 32-40 layers) 7-22 % faster, the two-wave ones of
+  // 12-28 layers 4-7 %; ragged FP32 batch 29.6 -> 25.4 ms.  At 10 layers it
+  // would cost the third wave per SIMD.
+  static constexpr bool pipelined(int lmax) { return lmax >= 12; }
 };
 
 // ---------------------------------------------------------------------------

@@ -42,10 +42,10 @@ BUDGET = {
         ("F32", 10, 0, 0, 0, 0): (168, 0, 0, 3, 12464),
     },
     ("nr_kernels_bucket.hip", ("F32", 20)): {
-        ("F32", 20, 0, 0, 0, 0): (256, 0, 44, 2, 19952),
+        ("F32", 20, 0, 0, 0, 0): (256, 0, 100, 2, 19952),
     },
     ("nr_kernels_bucket.hip", ("F32", 24)): {
-        ("F32", 24, 0, 0, 0, 0): (256, 0, 204, 2, 20080),
+        ("F32", 24, 0, 0, 0, 0): (256, 0, 260, 2, 20080),
     },
     ("nr_kernels_bucket.hip", ("F32", 40)): {
         ("F32", 40, 0, 0, 0, 0): (256, 228, 0, 1, 40048),
