@@ -42,7 +42,7 @@
 namespace nr {
 
 // Precision policies of the layer product.
-// kSlimMax: the deepest bucket whose store variant keeps only s^2 and f per
+// kSlimMax: the deepest bucket whose store variant keeps only g = s^2 f per
 // interface in registers and re-forms r' and kz_j kz_{j+1} in the adjoint
 // (8 more FMAs per level, 8 fewer registers).  Measured on MI355X: in FP64 it
 // lifts LMAX = 6 to two waves per SIMD (0.43 -> 0.45 of peak) but slows
@@ -216,27 +216,28 @@ __device__ __forceinline__ void stage_shared(Shared& s, int lane, const double* 
 }
 
 // Interface quantities shared by the forward and adjoint sweeps.
+// r' = r f = N s^2 f with N = w_j - w_{j+1} and s = 1/(kz_j + kz_{j+1}).  The
+// adjoint needs s^2 and f only through their product g = s^2 f: the
+// cotangent of r is conj(f) r'bar, and it reaches the wavevectors times
+// conj(s^2).
 template <class Re>
 struct Iface {
-  cx<Re> s2;  // 1/(kz_j + kz_{j+1})^2
-  cx<Re> f;   // Nevot-Croce factor
-  cx<Re> rp;  // r' = r f
+  cx<Re> g;   // s^2 f
+  cx<Re> rp;  // r' = N g
   cx<Re> kk;  // kz_j kz_{j+1}
 };
 
 // r = (w_j - w_{j+1}) / (kz_j + kz_{j+1})^2 = N s^2.  For identical media
-// N = 0 and r = 0 exactly: s^2 stays finite because |kz| >= 1e-75 (the root's
+// N = 0 and r' = 0 exactly: g stays finite because |kz| >= 1e-75 (the root's
 // guard), so no separate test is needed.
 template <class Re>
 __device__ __forceinline__ Iface<Re> interface_coeffs(const MathTables& T, cx<Re> kzc, cx<Re> kzn,
                                                       Re Nr, Re Ni, Re C) {
   Iface<Re> o;
   const cx<Re> s = crecip(kzc + kzn);
-  o.s2 = s * s;
-  const cx<Re> r = mk(Nr, Ni) * o.s2;
   o.kk = kzc * kzn;
-  o.f = cexp_tab(T, C * o.kk);
-  o.rp = r * o.f;
+  o.g = (s * s) * cexp_tab(T, C * o.kk);
+  o.rp = mk(Nr, Ni) * o.g;
   return o;
 }
 
@@ -524,9 +525,9 @@ struct AdjStep {
 //   Qbar_in = conj(r') Pbar + tbar
 //   rbar = conj(f) r'bar;  ubar = conj(r') r'bar   (u = C kz_j kz_{j+1}, f = e^u)
 //   r = (kz_j - kz_{j+1}) s: dr/dkz_j = 2 kz_{j+1} s^2, dr/dkz_{j+1} = -2 kz_j s^2
-//   kzbar_j     += conj(kz_{j+1}) (C ubar + 2 conj(s^2) rbar)
-//   kzbar_{j+1} += conj(kz_j)     (C ubar - 2 conj(s^2) rbar)
-//   e = exp(-2 i kz d): with w = conj(e) ebar,
+//   kzbar_j     += conj(kz_{j+1}) (C ubar + 2 Y)
+//   kzbar_{j+1} += conj(kz_j)     (C ubar - 2 Y),   Y = conj(s^2) rbar = conj(g) r'bar
+//   e = exp(-2 i kz d): with w = conj(e) ebar = conj(t) tbar,
 //   kzbar_j += i D w  (D = 2d),   dl/dd = 2 Im(kz_j conj(w))
 template <class Re>
 __device__ __forceinline__ AdjStep<Re> adjoint_step(cx<Re> Ps, cx<Re> Qs, cx<Re> Pb, cx<Re> Qb,
@@ -539,19 +540,17 @@ __device__ __forceinline__ AdjStep<Re> adjoint_step(cx<Re> Ps, cx<Re> Qs, cx<Re>
   o.w = mk(Re(0), Re(0));
   if (has_phase) {
     const Cx t = cmul_add(it.rp, Ps, Qs);
-    const Cx eb = cmulc(t, Qb);
     tb = cmulc(e, Qb);
-    o.w = cmulc(e, eb);
+    o.w = cmulc(t, tb);
   } else {
     tb = Qb;
   }
   const Cx rpb = cmulc_add(Ps, tb, cmulc(Qs, Pb));
   o.Pb = cmulc_add(it.rp, tb, Pb);
   o.Qb = cmulc_add(it.rp, Pb, tb);
-  const Cx rb = cmulc(it.f, rpb);
   o.ub = cmulc(it.rp, rpb);
   const Cx X = C * o.ub;
-  const Cx Y = cmulc(it.s2, rb);
+  const Cx Y = cmulc(it.g, rpb);
   const Cx Zc = mk(fma(Re(2), Y.re, X.re), fma(Re(2), Y.im, X.im));
   const Cx Zn = mk(fma(Re(-2), Y.re, X.re), fma(Re(-2), Y.im, X.im));
   o.kzb_c = cmulc_add(kzn, Zc, kzbc);
@@ -646,10 +645,10 @@ __device__ __forceinline__ double node_grad_store(const MathTables& T, const Lay
   const double kz0sq = kz0_squared(q);
   Cx kz[LMAX + 2];
   Re ia[LMAX + 2];
-  // per interface, kept for the adjoint: s^2 and the Nevot-Croce factor f,
-  // and unless the bucket is slim, r' and kz_j kz_{j+1} too
+  // per interface, kept for the adjoint: g = s^2 f, and unless the bucket is
+  // slim, r' and kz_j kz_{j+1} too
   constexpr bool kSlim = LMAX <= P::kSlimMax;
-  Cx ks2[LMAX + 1], kf[LMAX + 1];
+  Cx kg[LMAX + 1];
   Cx krp[kSlim ? 1 : LMAX + 1], kkk[kSlim ? 1 : LMAX + 1];
   Cx Pv = mk(Re(1), Re(0)), Qv = mk(Re(0), Re(0));
   {
@@ -670,8 +669,7 @@ __device__ __forceinline__ double node_grad_store(const MathTables& T, const Lay
       ia[jj] = rt.inv_abs2;
     }
     const Iface<Re> it = interface_coeffs(T, kz[jj], kz[jj + 1], L.Nr(jj), L.Ni(jj), L.C(jj));
-    ks2[jj] = it.s2;
-    kf[jj] = it.f;
+    kg[jj] = it.g;
     if constexpr (!kSlim) {
       krp[jj] = it.rp;
       kkk[jj] = it.kk;
@@ -699,10 +697,9 @@ __device__ __forceinline__ double node_grad_store(const MathTables& T, const Lay
   for (int jj = 0; jj <= LMAX; ++jj) {
     const Re C = L.C(jj);
     Iface<Re> it;
-    it.s2 = ks2[jj];
-    it.f = kf[jj];
+    it.g = kg[jj];
     if constexpr (kSlim) {
-      it.rp = (mk(L.Nr(jj), L.Ni(jj)) * it.s2) * it.f;
+      it.rp = mk(L.Nr(jj), L.Ni(jj)) * it.g;
       it.kk = kz[jj] * kz[jj + 1];
     } else {
       it.rp = krp[jj];
@@ -729,7 +726,8 @@ __device__ __forceinline__ double node_grad_store(const MathTables& T, const Lay
 }
 
 // LDS cache of the recompute variant: for levels 0..KS-1, the layer phase e
-// and the Nevot-Croce factor f (planes e.re, e.im, f.re, f.im, lane-minor).
+// and g = s^2 f, the Nevot-Croce factor times the squared interface
+// reciprocal (planes e.re, e.im, g.re, g.im, lane-minor).
 template <class Re, int KS>
 struct EfCache {
   Re v[KS][4][64];
@@ -737,8 +735,8 @@ struct EfCache {
 
 // ---------------------------------------------------------------------------
 // One node, recompute variant: the state tape stays in registers; the adjoint
-// recomputes each medium's wavevector and interface reciprocal, and, below
-// the KS cached levels, the phase and Nevot-Croce factor too.
+// recomputes each medium's wavevector, and, below the KS cached levels, the
+// interface reciprocal, the phase and the Nevot-Croce factor too.
 // ---------------------------------------------------------------------------
 template <class P, int LMAX, int KS, bool CK, bool RES>
 __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const Layers<P>& L,
@@ -781,7 +779,7 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
   // uses a region later; it loads the record of level jj-2.
   struct FwdPre {
     Cx kz;  // medium jj (jj = 0: the fronting medium)
-    Cx r;   // (w_jj - w_jj+1) s^2, r' without the Nevot-Croce factor
+    Cx s2;  // 1/(kz_jj + kz_jj+1)^2
     CexpPart<Re> f, e;
   };
   using Rec = typename Layers<P>::Rec;
@@ -795,7 +793,7 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
       o.kz = kz_root(static_cast<Re>(x), -rj.B).kz;
     }
     const Cx s = crecip(o.kz + kzb);
-    o.r = mk(rj.Nr, rj.Ni) * (s * s);
+    o.s2 = s * s;
     o.f = cexp_issue(T, rj.C * (o.kz * kzb));
     if (jj >= 1) o.e = cexp_issue(T, mk(rj.D * o.kz.im, -rj.D * o.kz.re));
     return o;
@@ -814,16 +812,16 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
         tapeP[CK ? jj / 2 : jj] = Pv;
         tapeQ[CK ? jj / 2 : jj] = Qv;
       }
-      const Cx f = cexp_finish(cur.f);
-      const Cx rp = cur.r * f;
+      const Cx g = cur.s2 * cexp_finish(cur.f);
+      const Cx rp = mk(R[jj].Nr, R[jj].Ni) * g;
       const Cx Pn = cmul_add(rp, Qv, Pv);
       const Cx t = cmul_add(rp, Pv, Qv);
       const Cx e = (jj >= 1) ? cexp_finish(cur.e) : mk(Re(1), Re(0));
       if (jj < KS) {
         ef.v[jj][0][lane] = e.re;
         ef.v[jj][1][lane] = e.im;
-        ef.v[jj][2][lane] = f.re;
-        ef.v[jj][3][lane] = f.im;
+        ef.v[jj][2][lane] = g.re;
+        ef.v[jj][3][lane] = g.im;
       }
       Qv = (jj >= 1) ? e * t : t;
       Pv = Pn;
@@ -845,8 +843,8 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
       if (jj < KS) {
         ef.v[jj][0][lane] = e.re;
         ef.v[jj][1][lane] = e.im;
-        ef.v[jj][2][lane] = it.f.re;
-        ef.v[jj][3][lane] = it.f.im;
+        ef.v[jj][2][lane] = it.g.re;
+        ef.v[jj][3][lane] = it.g.im;
       }
       Qv = (jj >= 1) ? e * t : t;
       Pv = Pn;
@@ -878,10 +876,8 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
     const bool ph = jj >= 1;
     o.D = ph ? L.D(jj) : Re(0);
     if (jj < KS) {
-      const Cx s = crecip(kzc + o.rn.kz);
-      o.it.s2 = s * s;
-      o.it.f = mk(ef.v[jj][2][lane], ef.v[jj][3][lane]);
-      o.it.rp = (mk(L.Nr(jj), L.Ni(jj)) * o.it.s2) * o.it.f;
+      o.it.g = mk(ef.v[jj][2][lane], ef.v[jj][3][lane]);
+      o.it.rp = mk(L.Nr(jj), L.Ni(jj)) * o.it.g;
       o.it.kk = kzc * o.rn.kz;
       o.e = ph ? mk(ef.v[jj][0][lane], ef.v[jj][1][lane]) : mk(Re(1), Re(0));
     } else {
@@ -915,26 +911,27 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
   // wavevector and interface and issues its table (or cache) reads.
   struct AdjPre {
     RootT<Re> rn;  // medium jj + 1
-    Cx s2, kk, r;  // s^2, kz_jj kz_jj+1, (w_jj - w_jj+1) s^2
-    Cx fv, ev;     // f and e from the LDS cache (jj < KS)
+    Cx s2, kk;     // s^2 (below the cache), kz_jj kz_jj+1
+    Cx gv, ev;     // g and e from the LDS cache (jj < KS)
     CexpPart<Re> f, e;
-    Re C, D;
+    Re C, D, Nr, Ni;
   };
   // (ri: the record of level jj, rn: that of medium jj + 1)
   auto adj_pre = [&](int jj, Cx kzb, const Rec& ri, const Rec& rn) {
     AdjPre o;
     o.rn = kz_root(static_cast<Re>(kz_real_part(kz0sq, rn.A)), -rn.B);
     o.C = ri.C;
+    o.Nr = ri.Nr;
+    o.Ni = ri.Ni;
     const bool ph = jj >= 1;
     o.D = ph ? ri.D : Re(0);
-    const Cx s = crecip(kzb + o.rn.kz);
-    o.s2 = s * s;
     o.kk = kzb * o.rn.kz;
-    o.r = mk(ri.Nr, ri.Ni) * o.s2;
     if (jj < KS) {
-      o.fv = mk(ef.v[jj][2][lane], ef.v[jj][3][lane]);
+      o.gv = mk(ef.v[jj][2][lane], ef.v[jj][3][lane]);
       o.ev = ph ? mk(ef.v[jj][0][lane], ef.v[jj][1][lane]) : mk(Re(1), Re(0));
     } else {
+      const Cx s = crecip(kzb + o.rn.kz);
+      o.s2 = s * s;
       o.f = cexp_issue(T, o.C * o.kk);
       if (ph) o.e = cexp_issue(T, mk(o.D * kzb.im, -o.D * kzb.re));
     }
@@ -945,10 +942,9 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
     o.rn = p.rn;
     o.C = p.C;
     o.D = p.D;
-    o.it.s2 = p.s2;
     o.it.kk = p.kk;
-    o.it.f = (jj < KS) ? p.fv : cexp_finish(p.f);
-    o.it.rp = p.r * o.it.f;
+    o.it.g = (jj < KS) ? p.gv : p.s2 * cexp_finish(p.f);
+    o.it.rp = mk(p.Nr, p.Ni) * o.it.g;
     o.e = (jj < 1) ? mk(Re(1), Re(0)) : (jj < KS) ? p.ev : cexp_finish(p.e);
     return o;
   };
