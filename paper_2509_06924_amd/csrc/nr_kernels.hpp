@@ -60,9 +60,9 @@ struct F64 {
   static constexpr int min_waves(int lmax, bool store, bool packed = false) {
     return ((!store && lmax <= 14) || (store && lmax <= 4 && !packed)) ? 2 : 1;
   }
-  // recompute variant: levels whose phase and Nevot-Croce factor are kept in
-  // LDS (2 KB per level per wave; ~36 KB of the 40 KB a wave may use at one
-  // wave per SIMD)
+  // recompute variant: levels whose phase e and g = s^2 f are kept in LDS
+  // (2 KB per level per wave; ~36 KB of the 40 KB a wave may use at one wave
+  // per SIMD)
   // (up to 10 layers the kernel fits two waves per SIMD in registers, so its
   // LDS is held to 20 KB: 8 levels)
   static constexpr int ef_levels(int lmax) {
@@ -75,8 +75,13 @@ struct F64 {
   static constexpr bool grouped_regions(int lmax) { return min_waves(lmax, false) == 1; }
   // one wave per SIMD leaves the latency of the table and record reads
   // exposed: the recompute variant then issues each level's reads one level
-  // ahead of their use
-  static constexpr bool pipelined(int lmax) { return min_waves(lmax, false) == 1; }
+  // ahead of their use.  The full units of 6 to 10 layers do so too, at two
+  // waves: 6 and 8 layers 5 and 4 % faster, the 4096-draw batch 1.3 %.  Their
+  // packed, split and resolution forms would spill 50-200 B per lane, so
+  // they keep per-level regions.
+  static constexpr bool pipelined(int lmax, bool packed_or_res = false) {
+    return min_waves(lmax, false) == 1 || (!packed_or_res && lmax >= 6 && lmax <= 10);
+  }
 };
 struct F32 {
   using real = float;
@@ -110,7 +115,7 @@ struct F32 {
   // one-wave kernels (16, 32-40 layers) 7-22 % faster, the two-wave ones of
   // 12-28 layers 4-7 %; ragged FP32 batch 29.6 -> 25.4 ms.  At 10 layers it
   // would cost the third wave per SIMD.
-  static constexpr bool pipelined(int lmax) { return lmax >= 12; }
+  static constexpr bool pipelined(int lmax, bool = false) { return lmax >= 12; }
 };
 
 // ---------------------------------------------------------------------------
@@ -738,7 +743,7 @@ struct EfCache {
 // recomputes each medium's wavevector, and, below the KS cached levels, the
 // interface reciprocal, the phase and the Nevot-Croce factor too.
 // ---------------------------------------------------------------------------
-template <class P, int LMAX, int KS, bool CK, bool RES>
+template <class P, int LMAX, int KS, bool CK, bool RES, bool PIPE>
 __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const Layers<P>& L,
                                                       EfCache<typename P::real, KS>& ef,
                                                       Accum<LMAX>& acc, int lane, double q,
@@ -762,8 +767,9 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
   // and phase of one level do not depend on the state, so the scheduler
   // overlaps neighbouring levels' chains.
   //
-  // Where the policy's pipelined says so (the one-wave kernels), both
-  // sweeps are software-pipelined instead: the region of one level also
+  // Where PIPE (the policy's pipelined) says so (the one-wave kernels, and the
+  // plain full units of 6 to 10 layers in FP64), both sweeps are
+  // software-pipelined instead: the region of one level also
   // forms the next level's wavevector and interface and issues its LDS table
   // (or cache) reads, and loads the layer record the region after it needs.
   // Each read then has a whole level of work to arrive in; left to the
@@ -771,7 +777,7 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
   // one wave stalled on it.
   constexpr bool kGrouped = P::grouped_regions(LMAX);
   constexpr int kAdjGroup = kGrouped ? 8 : 1;
-  constexpr bool kPipe = P::pipelined(LMAX);
+  constexpr bool kPipe = PIPE;
   Cx kzn = medium_root(L, kz0sq, LMAX + 1, edge).kz;
   Cx Pv = mk(Re(1), Re(0)), Qv = mk(Re(0), Re(0));
   // Pipelined forward sweep: the region of level jj also forms level jj-1's
@@ -1105,7 +1111,8 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE, TAIL || SPLIT)) void 
     if constexpr (STORE)
       R = node_grad_store<P, LMAX>(s.tab, L, tape, acc, lane, q, wk, edge);
     else
-      R = node_grad_recompute<P, LMAX, KS, P::checkpoint(LMAX), RES>(
+      R = node_grad_recompute<P, LMAX, KS, P::checkpoint(LMAX), RES,
+                              P::pipelined(LMAX, TAIL || SPLIT || RES)>(
           s.tab, L, efc, acc, lane, q, wk, edge, Hq, RES ? dq_dres * tk : 0.0);
     Rsm += wk * R;
   }

@@ -99,17 +99,33 @@ def test_resolution_gradient_matches_oracle(nr, orc, seed):
     assert smeared > 0
 
 
-def test_resolution_form_leaves_other_outputs_bitwise(nr):
+def test_resolution_form_leaves_other_outputs_unchanged(nr):
     """The resolution-derivative form is the recompute form plus one more
     accumulator: with the recompute form selected everywhere, logL and the
-    parameter gradient are bitwise those of nr_loglik_grad."""
+    parameter gradient are those of nr_loglik_grad.  Bitwise where the two
+    forms run the same schedule.  The plain full units of 6 to 10 layers are
+    software-pipelined and the resolution form's are not; the compiler then
+    fuses a few products into FMAs differently, so items in those buckets
+    agree to rounding."""
     batch = _batch(730, n_items=16)
     opts = {"grad_variant": {str(k): nr._n.NR_VARIANT_RECOMPUTE for k in nr.bucket_lmax()}}
     prob = nr.Problem.from_batch(batch, options=opts)
-    a = [t.cpu().numpy() for t in prob.loglik_grad()]
-    b = [t.cpu().numpy() for t in prob.loglik_grad_res()]
-    for x, y in zip(a, b[:3]):
-        assert np.array_equal(x, y)
+    llg_a, rows_a, inst_a = (t.cpu().numpy() for t in prob.loglik_grad())
+    llg_b, rows_b, inst_b = (t.cpu().numpy() for t in prob.loglik_grad_res()[:3])
+    L = np.diff(batch.row_off) - 2
+    buckets = np.array(sorted(nr.bucket_lmax()))
+    depth = buckets[np.searchsorted(buckets, L)]
+    piped = (depth >= 6) & (depth <= 10)
+    assert piped.any() and (~piped).any()
+    row_item = np.repeat(np.arange(batch.n_items), np.diff(batch.row_off))
+    for x, y, sel in ((llg_a, llg_b, piped), (inst_a, inst_b, piped),
+                      (rows_a, rows_b, piped[row_item])):
+        assert np.array_equal(x[~sel], y[~sel])
+    for b in np.flatnonzero(piped):
+        assert abs(llg_a[b] - llg_b[b]) <= 1e-12 * abs(llg_b[b])
+        ga = np.concatenate([rows_a[batch.row_off[b]:batch.row_off[b + 1]].ravel(), inst_a[b]])
+        gb = np.concatenate([rows_b[batch.row_off[b]:batch.row_off[b + 1]].ravel(), inst_b[b]])
+        assert np.max(np.abs(ga - gb)) <= 1e-11 * np.max(np.abs(gb)), f"item {b}"
 
 
 def test_item_dqq_override(nr, orc):
