@@ -233,9 +233,13 @@ __device__ __forceinline__ double kz0_squared(double q) {
 
 // Root of w = x + i y (y <= 0) with Re >= 0, Im <= 0, and 1/|w| = 1/|kz|^2:
 //   t = sqrt((|w| + |x|)/2), p = -y/(2t) (>= 0);  x >= 0 -> (t, -p), x < 0 -> (p, -t).
-// Both selects pick between non-negative values and the imaginary part is
-// negated after its select, so the negation folds into the source modifiers
-// of the instructions that use it.
+// Since t^2 - p^2 = |x|, t >= p, so with ts = t carrying the sign of x the
+// branch is Re = max(ts, p), Im = min(-p, ts): three instructions (the sign
+// is put on (|w| + |x|)/2 before its product with the reciprocal root, so
+// the maximum and minimum take arithmetic results) instead of a compare and
+// four selects.  Near x = 0, where t and p agree to rounding, either may be
+// taken.  The 1e-300 guard keeps t and p NaN together or finite together, so
+// the maximum and minimum, which drop a single NaN operand, never hide one.
 // A zero y with x < 0 gives (0, -sqrt|x|) whatever the sign of that zero.
 // |w|^2 gets 1e-300 added, which changes nothing unless w = 0 exactly, where
 // it yields kz of order 1e-75 instead of 0 (and keeps every value finite).
@@ -251,11 +255,11 @@ __device__ __forceinline__ Root kz_root(double x, double y) {
   const double m = a * ra;
   const double h = 0.5 * (m + fabs(x));
   const double rh = rsq(h);
-  const double t = h * rh;
+  const double ts = __builtin_copysign(h, x) * rh;
   const double p = -0.5 * (y * rh);
   Root out;
-  out.kz.re = (x >= 0.0) ? t : p;
-  out.kz.im = -((x >= 0.0) ? p : t);
+  out.kz.re = __builtin_fmax(ts, p);
+  out.kz.im = __builtin_fmin(-p, ts);
   out.inv_abs2 = ra;
   return out;
 }
@@ -300,9 +304,9 @@ struct CexpPart<float> {
 __device__ __forceinline__ CexpPart<float> cexp_issue(const MathTables&, cf z) { return {z}; }
 __device__ __forceinline__ cf cexp_finish(const CexpPart<float>& p) { return cexp_f32(p.z); }
 
-// The FP32 root of w = x + i y, same branch and values as kz_root(double,
-// double) (o = -p: negating after the select measured no faster in FP32); x
-// is the FP64 difference kz0^2 - A rounded once to float, so the
+// The FP32 root of w = x + i y, same branch as kz_root(double, double), with
+// selects (o = -p; the select-free FP64 form is not measured in FP32); x is
+// the FP64 difference kz0^2 - A rounded once to float, so the
 // cancellation near a critical edge happens in FP64.  |w|^2 gets 1e-36 added
 // (a floor of 1e-18 on |w|), which keeps w = 0 finite.
 __device__ __forceinline__ RootT<float> kz_root(float x, float y) {
