@@ -305,8 +305,8 @@ __device__ __forceinline__ CexpPart<float> cexp_issue(const MathTables&, cf z) {
 __device__ __forceinline__ cf cexp_finish(const CexpPart<float>& p) { return cexp_f32(p.z); }
 
 // The FP32 root of w = x + i y, same branch as kz_root(double, double), with
-// selects (o = -p; the select-free FP64 form is not measured in FP32); x is
-// the FP64 difference kz0^2 - A rounded once to float, so the
+// selects (o = -p): the select-free form gives the same bits in FP32 but
+// measured 2 % slower on the 4096-draw batch; x is the FP64 difference kz0^2 - A rounded once to float, so the
 // cancellation near a critical edge happens in FP64.  |w|^2 gets 1e-36 added
 // (a floor of 1e-18 on |w|), which keeps w = 0 finite.
 __device__ __forceinline__ RootT<float> kz_root(float x, float y) {
