@@ -74,7 +74,12 @@ __global__ __launch_bounds__(256) void k_reduce_loglik(ReduceArgs a) {
 // One block per item of 64 x W threads (W from the plan's deepest item, so
 // that the thousands of fields of a deep item's records are spread over
 // many waves): threads sum record fields over the item's WUs, then turn the
-// sums into gradients of the row entries.
+// sums into gradients of the row entries.  With gridDim.y = 4 (plans with
+// deep items) an item has four blocks, one per plane of the record (sum
+// Re wbar, sum Im wbar, the d sums, the sigma sums): each row-gradient
+// column comes from one plane, so the blocks need nothing from each other,
+// and a deep item's reduction spreads over four compute units.  Block 0
+// also takes the leading fields and the resolution field.
 __global__ __launch_bounds__(1024) void k_reduce_grad(ReduceArgs a) {
   extern __shared__ double fsum[];
   __shared__ int64_t offs[64];
@@ -89,43 +94,62 @@ __global__ __launch_bounds__(1024) void k_reduce_grad(ReduceArgs a) {
   // records hold 4 + 4 NR doubles; the last is written by the resolution
   // form only
   const int nf = (a.g_res ? 4 : 3) + 4 * NR;
+  const bool by_plane = gridDim.y == 4;
+  const int plane = blockIdx.y;
+  const bool lead = !by_plane || plane == 0;  // this block's fields include 0, 1, 2
+  // the fields this block sums: all nf, or plane `plane` (NR fields) and, for
+  // plane 0, the leading ones; field of the block's i-th: fld(i)
+  const int nmine = by_plane ? NR + (plane == 0 ? nf - 4 * NR : 0) : nf;
+  auto fld = [&](int i) {
+    if (!by_plane) return i;
+    if (i < NR) return 3 + plane * NR + i;
+    return (i - NR < 3) ? i - NR : 3 + 4 * NR;
+  };
   // The units' record offsets are staged 64 at a time (one load per
   // thread), so the record loads of a chunk are independent of each other
   // instead of each waiting for its offset; the sum runs over the units in
-  // order.
+  // order.  A thread issues 32 record loads before it adds them (in order):
+  // an item with few units but thousands of fields (a deep stack) has few
+  // blocks, so its time is the latency of these loads.
+  constexpr int kAhead = 32;
   for (int k0 = 0; k0 < cnt; k0 += 64) {
     const int kc = min(64, cnt - k0);
     __syncthreads();  // the previous chunk's offsets are no longer read
     if (tid < kc) offs[tid] = a.rec_of_wu[first + k0 + tid];
     __syncthreads();
-    for (int f = tid; f < nf; f += nt) {
+    for (int i = tid; i < nmine; i += nt) {
+      const int f = fld(i);
       double v = (k0 == 0) ? 0.0 : fsum[f];
+      int k = 0;
+      for (; k + kAhead <= kc; k += kAhead) {
+        double r[kAhead];
+#pragma unroll
+        for (int j = 0; j < kAhead; ++j) r[j] = a.rec[offs[k + j] + f];
+#pragma unroll
+        for (int j = 0; j < kAhead; ++j) v += r[j];
+      }
 #pragma unroll 8
-      for (int k = 0; k < kc; ++k) v += a.rec[offs[k] + f];
+      for (; k < kc; ++k) v += a.rec[offs[k] + f];
       fsum[f] = v;
     }
   }
   if (cnt <= 0)
-    for (int f = tid; f < nf; f += nt) fsum[f] = 0.0;
+    for (int i = tid; i < nmine; i += nt) fsum[fld(i)] = 0.0;
   __syncthreads();
   const double* rows = a.layers + 4 * roff;
   double* g = a.g_rows + 4 * roff;
   for (int m = tid; m < NR; m += nt) {
-    const double wr = fsum[3 + m], wi = fsum[3 + NR + m];
-    const double dd = fsum[3 + 2 * NR + m], ss = fsum[3 + 3 * NR + m];
-    double gd = 0.0, gre = 0.0, gim = 0.0, gsig = 0.0;
-    if (m >= 1) {
-      gre = -kFourPi * wr;
+    // column c of row m comes from plane (c + 2) % 4 of the record
+    if (!by_plane || plane == 2) g[4 * m + 0] = (m >= 1 && m <= NR - 2) ? fsum[3 + 2 * NR + m] : 0.0;
+    if (!by_plane || plane == 0) g[4 * m + 1] = (m >= 1) ? -kFourPi * fsum[3 + m] : 0.0;
+    if (!by_plane || plane == 1) {
       const double sgn = (rows[4 * m + 2] < 0.0) ? -1.0 : 1.0;
-      gim = -kFourPi * sgn * wi;
-      gsig = -4.0 * rows[4 * m + 3] * ss;
-      if (m <= NR - 2) gd = dd;
+      g[4 * m + 2] = (m >= 1) ? -kFourPi * sgn * fsum[3 + NR + m] : 0.0;
     }
-    g[4 * m + 0] = gd;
-    g[4 * m + 1] = gre;
-    g[4 * m + 2] = gim;
-    g[4 * m + 3] = gsig;
+    if (!by_plane || plane == 3)
+      g[4 * m + 3] = (m >= 1) ? -4.0 * rows[4 * m + 3] * fsum[3 + 3 * NR + m] : 0.0;
   }
+  if (!lead) return;
   // fronting rho_re: the model depends on rho_re,m - rho_re,0 only; the
   // waves' partial sums are added in wave order
   double part = 0.0;
@@ -192,9 +216,11 @@ hipError_t launch_reduce(int op, const ReduceArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_reduce_loglik, dim3((a.n_items + 255) / 256), dim3(256), 0, st, a);
   } else {
     const size_t shmem = sizeof(double) * (4 + 4 * (size_t)a.max_rows);
-    // one wave per 64 rows of the deepest item, at most 16
+    // one wave per 64 rows of the deepest item, at most 16; beyond 64 rows,
+    // one block per record plane and item
     const int waves = std::min(16, std::max(1, (a.max_rows + 63) / 64));
-    hipLaunchKernelGGL(k_reduce_grad, dim3(a.n_items), dim3(64 * waves), shmem, st, a);
+    const int planes = a.max_rows > 64 ? 4 : 1;
+    hipLaunchKernelGGL(k_reduce_grad, dim3(a.n_items, planes), dim3(64 * waves), shmem, st, a);
   }
   return hipGetLastError();
 }
