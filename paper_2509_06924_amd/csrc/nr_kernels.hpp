@@ -61,12 +61,16 @@ struct F64 {
     return ((!store && lmax <= 14) || (store && lmax <= 4 && !packed)) ? 2 : 1;
   }
   // recompute variant: levels whose phase e and g = s^2 f are kept in LDS
-  // (2 KB per level per wave; ~36 KB of the 40 KB a wave may use at one wave
-  // per SIMD)
-  // (up to 10 layers the kernel fits two waves per SIMD in registers, so its
-  // LDS is held to 20 KB: 8 levels)
+  // (2 KB per level per wave), and below them e_levels levels whose phase
+  // alone is kept (1 KB each).  A wave may use 20 KB at two waves per SIMD
+  // (up to 14 layers): 8 + 1 levels; 40 KB at one wave: 18 + 1 levels.
+  // With the rule, the tables (2.8 KB) and the record staging sharing the
+  // cache, that fills both budgets to within 240 B.
   static constexpr int ef_levels(int lmax) {
-    return lmax <= 14 ? (lmax + 1 < 8 ? lmax + 1 : 8) : (lmax + 1 < 17 ? lmax + 1 : 17);
+    return lmax <= 14 ? (lmax + 1 < 8 ? lmax + 1 : 8) : (lmax + 1 < 18 ? lmax + 1 : 18);
+  }
+  static constexpr int e_levels(int lmax) {
+    return lmax + 1 > ef_levels(lmax) ? 1 : 0;
   }
   // recompute variant: keep the state of every second level only (the
   // register tape of the deepest buckets otherwise spills to scratch)
@@ -105,6 +109,7 @@ struct F32 {
            : lmax <= 28 ? (lmax + 1 < 16 ? lmax + 1 : 16)
                         : (lmax + 1 < 35 ? lmax + 1 : 35);
   }
+  static constexpr int e_levels(int) { return 0; }
   static constexpr bool checkpoint(int lmax) { return lmax == 18 || lmax == 20 || lmax >= 24; }
   // from 12 layers, at one or two waves per SIMD (12 layers 5 % faster, 14-28
   // equal or faster); not at 32-40 layers (3-5 % slower)
@@ -622,7 +627,7 @@ struct Accum {
 // layer phase, as separate real and imaginary planes, lane-minor (a level's
 // two planes are 64 elements apart, one ds_write2/ds_read2 per value).
 template <class Re, int LMAX>
-struct GradTape {
+struct alignas(16) GradTape {
   Re P[LMAX + 1][2][64], Qv[LMAX + 1][2][64], E[LMAX + 1][2][64];
 };
 
@@ -732,10 +737,25 @@ __device__ __forceinline__ double node_grad_store(const MathTables& T, const Lay
 
 // LDS cache of the recompute variant: for levels 0..KS-1, the layer phase e
 // and g = s^2 f, the Nevot-Croce factor times the squared interface
-// reciprocal (planes e.re, e.im, g.re, g.im, lane-minor).
-template <class Re, int KS>
-struct EfCache {
+// reciprocal (planes e.re, e.im, g.re, g.im, lane-minor); for levels
+// KS..KS+KE-1 the phase alone.
+template <class Re, int KS, int KE>
+struct alignas(16) EfCache {
   Re v[KS][4][64];
+  Re ve[KE][2][64];
+  __device__ __forceinline__ cx<Re> e_extra(int jj, int lane) const {
+    return mk(ve[jj - KS][0][lane], ve[jj - KS][1][lane]);
+  }
+  __device__ __forceinline__ void put_e_extra(int jj, int lane, cx<Re> e) {
+    ve[jj - KS][0][lane] = e.re;
+    ve[jj - KS][1][lane] = e.im;
+  }
+};
+template <class Re, int KS>
+struct alignas(16) EfCache<Re, KS, 0> {
+  Re v[KS][4][64];
+  __device__ __forceinline__ cx<Re> e_extra(int, int) const { return mk(Re(0), Re(0)); }
+  __device__ __forceinline__ void put_e_extra(int, int, cx<Re>) {}
 };
 
 // ---------------------------------------------------------------------------
@@ -743,9 +763,9 @@ struct EfCache {
 // recomputes each medium's wavevector, and, below the KS cached levels, the
 // interface reciprocal, the phase and the Nevot-Croce factor too.
 // ---------------------------------------------------------------------------
-template <class P, int LMAX, int KS, bool CK, bool RES, bool PIPE>
+template <class P, int LMAX, int KS, int KE, bool CK, bool RES, bool PIPE>
 __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const Layers<P>& L,
-                                                      EfCache<typename P::real, KS>& ef,
+                                                      EfCache<typename P::real, KS, KE>& ef,
                                                       Accum<LMAX>& acc, int lane, double q,
                                                       double wk, bool& edge, double& Hq,
                                                       double c) {
@@ -828,6 +848,8 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
         ef.v[jj][1][lane] = e.im;
         ef.v[jj][2][lane] = g.re;
         ef.v[jj][3][lane] = g.im;
+      } else if (jj < KS + KE) {
+        ef.put_e_extra(jj, lane, e);
       }
       Qv = (jj >= 1) ? e * t : t;
       Pv = Pn;
@@ -851,6 +873,8 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
         ef.v[jj][1][lane] = e.im;
         ef.v[jj][2][lane] = it.g.re;
         ef.v[jj][3][lane] = it.g.im;
+      } else if (jj < KS + KE) {
+        ef.put_e_extra(jj, lane, e);
       }
       Qv = (jj >= 1) ? e * t : t;
       Pv = Pn;
@@ -888,7 +912,8 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
       o.e = ph ? mk(ef.v[jj][0][lane], ef.v[jj][1][lane]) : mk(Re(1), Re(0));
     } else {
       o.it = interface_coeffs(T, kzc, o.rn.kz, L.Nr(jj), L.Ni(jj), o.C);
-      o.e = ph ? layer_phase(T, kzc, o.D) : mk(Re(1), Re(0));
+      o.e = !ph ? mk(Re(1), Re(0))
+                : (jj < KS + KE) ? ef.e_extra(jj, lane) : layer_phase(T, kzc, o.D);
     }
     return o;
   };
@@ -918,7 +943,7 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
   struct AdjPre {
     RootT<Re> rn;  // medium jj + 1
     Cx s2, kk;     // s^2 (below the cache), kz_jj kz_jj+1
-    Cx gv, ev;     // g and e from the LDS cache (jj < KS)
+    Cx gv, ev;     // g (jj < KS) and e (jj < KS + KE) from the LDS cache
     CexpPart<Re> f, e;
     Re C, D, Nr, Ni;
   };
@@ -939,7 +964,12 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
       const Cx s = crecip(kzb + o.rn.kz);
       o.s2 = s * s;
       o.f = cexp_issue(T, o.C * o.kk);
-      if (ph) o.e = cexp_issue(T, mk(o.D * kzb.im, -o.D * kzb.re));
+      if (ph) {
+        if (jj < KS + KE)
+          o.ev = ef.e_extra(jj, lane);
+        else
+          o.e = cexp_issue(T, mk(o.D * kzb.im, -o.D * kzb.re));
+      }
     }
     return o;
   };
@@ -951,7 +981,7 @@ __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const
     o.it.kk = p.kk;
     o.it.g = (jj < KS) ? p.gv : p.s2 * cexp_finish(p.f);
     o.it.rp = mk(p.Nr, p.Ni) * o.it.g;
-    o.e = (jj < 1) ? mk(Re(1), Re(0)) : (jj < KS) ? p.ev : cexp_finish(p.e);
+    o.e = (jj < 1) ? mk(Re(1), Re(0)) : (jj < KS + KE) ? p.ev : cexp_finish(p.e);
     return o;
   };
   // records of media 0 .. LMAX + 1, each loaded a region before its use
@@ -1073,7 +1103,8 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE, TAIL || SPLIT)) void 
   using Tape = typename std::conditional<STORE, GradTape<Re, LMAX>, char>::type;
   __shared__ Tape tape;
   constexpr int KS = STORE ? 1 : P::ef_levels(LMAX);
-  using Ef = typename std::conditional<STORE, char, EfCache<Re, KS>>::type;
+  constexpr int KE = STORE ? 0 : P::e_levels(LMAX);
+  using Ef = typename std::conditional<STORE, char, EfCache<Re, KS, KE>>::type;
   __shared__ Ef efc;
   const int lane = threadIdx.x;
   const int w = blockIdx.x;
@@ -1111,7 +1142,7 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE, TAIL || SPLIT)) void 
     if constexpr (STORE)
       R = node_grad_store<P, LMAX>(s.tab, L, tape, acc, lane, q, wk, edge);
     else
-      R = node_grad_recompute<P, LMAX, KS, P::checkpoint(LMAX), RES,
+      R = node_grad_recompute<P, LMAX, KS, KE, P::checkpoint(LMAX), RES,
                               P::pipelined(LMAX, TAIL || SPLIT || RES)>(
           s.tab, L, efc, acc, lane, q, wk, edge, Hq, RES ? dq_dres * tk : 0.0);
     Rsm += wk * R;
@@ -1222,7 +1253,12 @@ __global__ __launch_bounds__(64, P::min_waves(LMAX, STORE, TAIL || SPLIT)) void 
     return;
   }
   // ---- wave reduction; the sums go through LDS into one coalesced store ----
-  __shared__ double stage[4 + 4 * (LMAX + 2)];
+  // (staged in the unit's tape or cache, which the sweeps no longer read; a
+  // block is one wave, so its LDS accesses stay in program order)
+  using Sweep = typename std::conditional<STORE, Tape, Ef>::type;
+  static_assert(sizeof(Sweep) >= sizeof(double) * (4 + 4 * (LMAX + 2)),
+                "the record staging must fit in the sweep's LDS");
+  double* stage = STORE ? reinterpret_cast<double*>(&tape) : reinterpret_cast<double*>(&efc);
   ll = wave_sum(ll);
   gsc = wave_sum(gsc);
   gbk = wave_sum(gbk);

@@ -21,34 +21,34 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Expected: (VGPRs, AGPRs, scratch bytes per lane, waves per SIMD, LDS bytes).
 BUDGET = {
     ("nr_kernels_f64.hip", ()): {
-        ("F64", 4, 1, 0, 0, 0): (239, 0, 0, 2, 18416),
-        ("F64", 10, 1, 0, 0, 0): (256, 232, 0, 1, 37040),
-        ("F64", 10, 0, 0, 0, 0): (255, 0, 12, 2, 19632),
-        ("F64", 10, 0, 0, 1, 0): (245, 0, 0, 2, 19632),
-        ("F64", 10, 0, 0, 0, 1): (254, 0, 20, 2, 19632),
-        ("F64", 12, 0, 0, 0, 0): (247, 0, 0, 2, 19696),
+        ("F64", 4, 1, 0, 0, 0): (237, 0, 0, 2, 18192),
+        ("F64", 10, 1, 0, 0, 0): (256, 232, 0, 1, 36624),
+        ("F64", 10, 0, 0, 0, 0): (255, 0, 12, 2, 20240),
+        ("F64", 10, 0, 0, 1, 0): (245, 0, 0, 2, 20240),
+        ("F64", 10, 0, 0, 0, 1): (254, 0, 20, 2, 20240),
+        ("F64", 12, 0, 0, 0, 0): (247, 0, 0, 2, 20240),
     },
     ("nr_kernels_bucket.hip", ("F64", 14)): {
-        ("F64", 14, 0, 0, 0, 0): (255, 0, 60, 2, 19760),
+        ("F64", 14, 0, 0, 0, 0): (255, 0, 60, 2, 20240),
     },
     ("nr_kernels_bucket.hip", ("F64", 24)): {
-        ("F64", 24, 0, 0, 0, 0): (256, 224, 0, 1, 38512),
+        ("F64", 24, 0, 0, 0, 0): (256, 224, 0, 1, 40720),
     },
     ("nr_kernels_bucket.hip", ("F64", 40)): {
-        ("F64", 40, 0, 0, 0, 0): (256, 256, 400, 1, 39024),
+        ("F64", 40, 0, 0, 0, 0): (256, 256, 400, 1, 40720),
     },
     ("nr_kernels_f32.hip", ()): {
-        ("F32", 8, 1, 0, 0, 0): (239, 0, 0, 2, 17008),
-        ("F32", 10, 0, 0, 0, 0): (167, 0, 0, 3, 12464),
+        ("F32", 8, 1, 0, 0, 0): (239, 0, 0, 2, 16656),
+        ("F32", 10, 0, 0, 0, 0): (167, 0, 0, 3, 12048),
     },
     ("nr_kernels_bucket.hip", ("F32", 20)): {
-        ("F32", 20, 0, 0, 0, 0): (256, 0, 68, 2, 19952),
+        ("F32", 20, 0, 0, 0, 0): (256, 0, 68, 2, 19216),
     },
     ("nr_kernels_bucket.hip", ("F32", 24)): {
-        ("F32", 24, 0, 0, 0, 0): (256, 0, 228, 2, 20080),
+        ("F32", 24, 0, 0, 0, 0): (256, 0, 228, 2, 19216),
     },
     ("nr_kernels_bucket.hip", ("F32", 40)): {
-        ("F32", 40, 0, 0, 0, 0): (256, 220, 0, 1, 40048),
+        ("F32", 40, 0, 0, 0, 0): (256, 220, 0, 1, 38672),
     },
     ("nr_kernels_scan.hip", ()): {
         ("scan", 8, 1, 0): (253, 0, 0, 2, 19216),
