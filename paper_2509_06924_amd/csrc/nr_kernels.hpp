@@ -101,13 +101,15 @@ struct F32 {
     return (lmax <= 28 && lmax != 16) ? 2 : 1;
   }
   // 1 KB per level; up to 28 layers the LDS of a kernel that may share the
-  // SIMD with a second wave stays within 20 KB; up to 10 layers the kernel
-  // fits three waves per SIMD in registers, and 9 levels keep its LDS within
-  // 160 KB / 12 waves (at 11 levels only 11 waves fit a CU: 3-5 % slower)
+  // SIMD with a second wave stays within 20 KB (17 levels, the record
+  // staging sharing the cache); beyond, 37 levels within 40 KB; up to 10
+  // layers the kernel fits three waves per SIMD in registers, and 9 levels
+  // keep its LDS within 160 KB / 12 waves (10 levels fit too but measured
+  // 2.5 % slower; at 11 levels only 11 waves fit a CU: 3-5 % slower)
   static constexpr int ef_levels(int lmax) {
     return lmax <= 10   ? (lmax + 1 < 9 ? lmax + 1 : 9)
-           : lmax <= 28 ? (lmax + 1 < 16 ? lmax + 1 : 16)
-                        : (lmax + 1 < 35 ? lmax + 1 : 35);
+           : lmax <= 28 ? (lmax + 1 < 17 ? lmax + 1 : 17)
+                        : (lmax + 1 < 37 ? lmax + 1 : 37);
   }
   static constexpr int e_levels(int) { return 0; }
   static constexpr bool checkpoint(int lmax) { return lmax == 18 || lmax == 20 || lmax >= 24; }

@@ -42,13 +42,13 @@ BUDGET = {
         ("F32", 10, 0, 0, 0, 0): (167, 0, 0, 3, 12048),
     },
     ("nr_kernels_bucket.hip", ("F32", 20)): {
-        ("F32", 20, 0, 0, 0, 0): (256, 0, 68, 2, 19216),
+        ("F32", 20, 0, 0, 0, 0): (256, 0, 68, 2, 20240),
     },
     ("nr_kernels_bucket.hip", ("F32", 24)): {
-        ("F32", 24, 0, 0, 0, 0): (256, 0, 228, 2, 19216),
+        ("F32", 24, 0, 0, 0, 0): (256, 0, 228, 2, 20240),
     },
     ("nr_kernels_bucket.hip", ("F32", 40)): {
-        ("F32", 40, 0, 0, 0, 0): (256, 220, 0, 1, 38672),
+        ("F32", 40, 0, 0, 0, 0): (256, 220, 0, 1, 40720),
     },
     ("nr_kernels_scan.hip", ()): {
         ("scan", 8, 1, 0): (253, 0, 0, 2, 19216),
