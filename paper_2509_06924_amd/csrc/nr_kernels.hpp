@@ -762,8 +762,9 @@ struct alignas(16) EfCache<Re, KS, 0> {
 
 // ---------------------------------------------------------------------------
 // One node, recompute variant: the state tape stays in registers; the adjoint
-// recomputes each medium's wavevector, and, below the KS cached levels, the
-// interface reciprocal, the phase and the Nevot-Croce factor too.
+// recomputes each medium's wavevector; below the KS cached levels also the
+// interface reciprocal and the Nevot-Croce factor, and below the KE levels
+// after them, whose phase alone is cached, the phase.
 // ---------------------------------------------------------------------------
 template <class P, int LMAX, int KS, int KE, bool CK, bool RES, bool PIPE>
 __device__ __forceinline__ double node_grad_recompute(const MathTables& T, const Layers<P>& L,
