@@ -254,17 +254,9 @@ __device__ __forceinline__ Root kz_root(double x, double y) {
   const double ra = rsq(a);
   const double m = a * ra;
   const double h = 0.5 * (m + fabs(x));
-  // ts = sqrt(h) with the sign of x and hh = 1/(2 sqrt(h)) by one coupled
-  // (Goldschmidt) step from the hardware estimate y0 of 1/sqrt(h): with
-  // y0 = (1 + d)/sqrt(h), r = 1/2 - |g| hh = -(d + d^2/2), and g (1 + r),
-  // hh (1 + r) carry a relative error of 3 d^2 / 2, as one Newton step of
-  // the reciprocal root does, in one instruction fewer
-  const double y0 = __builtin_amdgcn_rsq(h);
-  const double g = __builtin_copysign(h, x) * y0;
-  const double hh = 0.5 * y0;
-  const double r = fma(-fabs(g), hh, 0.5);
-  const double ts = fma(g, r, g);
-  const double p = -y * fma(hh, r, hh);
+  const double rh = rsq(h);
+  const double ts = __builtin_copysign(h, x) * rh;
+  const double p = -0.5 * (y * rh);
   Root out;
   out.kz.re = __builtin_fmax(ts, p);
   out.kz.im = __builtin_fmin(-p, ts);

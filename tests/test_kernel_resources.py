@@ -25,7 +25,7 @@ BUDGET = {
         ("F64", 10, 1, 0, 0, 0): (256, 232, 0, 1, 36624),
         ("F64", 10, 0, 0, 0, 0): (255, 0, 12, 2, 20240),
         ("F64", 10, 0, 0, 1, 0): (245, 0, 0, 2, 20240),
-        ("F64", 10, 0, 0, 0, 1): (254, 0, 12, 2, 20240),
+        ("F64", 10, 0, 0, 0, 1): (254, 0, 20, 2, 20240),
         ("F64", 12, 0, 0, 0, 0): (247, 0, 0, 2, 20240),
     },
     ("nr_kernels_bucket.hip", ("F64", 14)): {
